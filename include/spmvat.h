@@ -1,0 +1,244 @@
+/*
+ * spmvat.h -- run-time CRS transformation and auto-tuned SpMV on AMD MI355X
+ * (gfx950), after Katagiri & Sato, "An Auto-tuning Method for Run-time Data
+ * Transformation for Sparse Matrix-Vector Multiplication" (arXiv:2407.00019).
+ *
+ * Conventions for every entry point
+ *  - Matrices are square, n x n (section 2.1).  Indices are 0-based int32:
+ *    the paper's 1-based IRP(1)=1 ... IRP(N+1)=NNZ+1 is irp[0]=0 ...
+ *    irp[n]=nnz here.  1 <= n and 0 <= nnz <= INT32_MAX.
+ *  - "device" pointers are HIP device memory of the current device; every
+ *    device array must be 16-byte aligned (SPMV_E_ARG otherwise).
+ *  - `stream` is a hipStream_t passed as void* (NULL: the default stream).
+ *    Work is enqueued on it; unless stated, calls return before it runs.
+ *  - The caller owns every device buffer.  A plan *borrows* the CRS arrays
+ *    and every buffer handed to a transformation: they must stay alive and
+ *    unchanged while the plan may use them.  The plan itself is host memory.
+ *  - Errors are returned as spmv_status; nothing aborts, prints or throws.
+ *    On an error no device work has been enqueued unless stated, and formats
+ *    built earlier on the plan stay usable.
+ *  - Calls on different plans may run concurrently from different host
+ *    threads and streams.  Calls on one plan that overlap in time (two
+ *    streams, or two host threads) race on the plan's workspace.
+ *  - Floating-point inputs must be finite (0 * Inf in ELL padding is NaN).
+ */
+#ifndef SPMVAT_H
+#define SPMVAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPMV_OK = 0,
+    SPMV_E_ARG = 1,        /* bad argument: null, size, enum, alignment, short buffer */
+    SPMV_E_MATRIX = 2,     /* the CRS arrays break the contract (see spmv_plan_create) */
+    SPMV_E_TOO_LARGE = 3,  /* the format would exceed the plan's memory limit */
+    SPMV_E_NOT_READY = 4,  /* the format, or the CCS it needs, is not built yet */
+    SPMV_E_HIP = 5         /* a HIP runtime error; see spmv_plan_last_error */
+} spmv_status;
+
+/* Storage formats of section 2.1.  CRS: VAL/ICOL/IRP.  COO_ROW: CRS VAL and
+ * ICOL plus IROW.  CCS: column pointers, row numbers, values (Phase I of the
+ * column-wise transformation).  COO_COL: the CCS arrays plus a column index
+ * per entry (Phase II).  ELL_ROW / ELL_COL: VAL(n, nz) and the index array
+ * of the same shape, zero padded. */
+typedef enum {
+    SPMV_CRS = 0, SPMV_COO_ROW = 1, SPMV_CCS = 2,
+    SPMV_COO_COL = 3, SPMV_ELL_ROW = 4, SPMV_ELL_COL = 5
+} spmv_format;
+
+/* Value storage.  F64 values take F64 x and y; F32, BF16 and F16 values take
+ * F32 x and y and accumulate in F32 (reduced-precision storage, an extension
+ * beyond the paper).  Index arrays are int32 in every case. */
+typedef enum { SPMV_F64 = 0, SPMV_F32 = 1, SPMV_BF16 = 2, SPMV_F16 = 3 } spmv_dtype;
+
+typedef struct spmv_plan spmv_plan;
+
+/* Row statistics behind D_mat, Eq. (4).  l_i = irp[i+1] - irp[i] counts every
+ * stored entry of row i.  sum_len and sum_len2 are exact; mu = sum_len / n;
+ * sigma is the population standard deviation; d_mat = sigma / mu (0 when
+ * nnz = 0), each rounded once from the exact integers: with
+ * num = n*sum_len2 - sum_len^2 rounded to binary64, sigma = sqrt(num) / n and
+ * d_mat = sqrt(num) / sum_len.  max_col is the longest column (the ELL-Column
+ * width), -1 until csr_to_ccs has run. */
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    int64_t sum_len, sum_len2;
+    int32_t max_row, min_row, max_col;
+    double mu, sigma, d_mat;
+} spmv_stats;
+
+/* Bytes of every device array a transformation writes (index order as in
+ * spmv_buffers), the scratch workspace it needs, and the ELL width. */
+typedef struct {
+    size_t bytes[4];
+    size_t workspace;
+    int32_t width;
+} spmv_sizes;
+
+/* Output arrays of a transformation and their sizes in bytes.
+ *   COO_ROW: ptr[0] irow[nnz] int32
+ *   CCS:     ptr[0] ccp[n+1] int32, ptr[1] irow_t[nnz] int32, ptr[2] val_t[nnz]
+ *   COO_COL: ptr[0] jcol[nnz] int32 (with the CCS arrays already built)
+ *   ELL_ROW: ptr[0] ell_val[width*n], ptr[1] ell_col[width*n] int32
+ *   ELL_COL: ptr[0] ell_val[width*n], ptr[1] ell_row[width*n] int32
+ * ELL arrays are slot-major (the paper's Fortran VAL(1:n,1:nz)): slot k of
+ * line i at k*n + i. */
+typedef struct {
+    void *ptr[4];
+    size_t bytes[4];
+} spmv_buffers;
+
+/* Auto-tuning table: the off-line phase's result (section 2.2) plus a cost
+ * model for the amortised (k-aware) decision.  D bucket b = min(7,
+ * floor(D_mat / 0.5)).  Rates are algorithmic bytes per second; 0 marks a
+ * missing entry. */
+#define AT_DBUCKETS 8
+typedef struct {
+    double c;                              /* R_ell threshold (the paper uses 1.0) */
+    double d_star;                         /* ELL-Row when D_mat < d_star; +inf: always */
+    int32_t calibrated;                    /* 1 when the cost model is filled */
+    double spmv_bps[6][2][AT_DBUCKETS];    /* [format][variant][bucket] SpMV rate */
+    double trans_bps[6][AT_DBUCKETS];      /* [format][bucket] transformation rate */
+    double launch_s;                       /* fixed cost added per kernel launch */
+} at_table;
+
+typedef struct {
+    int32_t rule;          /* 0: paper rule (D_mat vs D*), 1: k-aware cost model */
+    int32_t feasible_ell;  /* ELL-Row fits the plan's memory limit */
+    double d_mat;
+    double t_crs_hat;      /* estimated CRS SpMV seconds (best CRS variant) */
+    double t_fmt_hat;      /* estimated SpMV seconds in the chosen format */
+    double t_trans_hat;    /* estimated transformation seconds into it */
+    double k_break_even;   /* TT / (1 - 1/SP) for the chosen format; 0 for CRS */
+} at_decision;
+
+/* ------------------------------------------------------------- planning */
+
+/* Bytes of the per-plan device workspace for an n x n matrix with nnz
+ * entries (row-statistics partials and SpMV carries). */
+size_t spmv_plan_workspace_bytes(int32_t n, int64_t nnz);
+
+/* Creates a plan over a CRS matrix (section 2.1) and computes its row
+ * statistics (Eq. (4)) on the GPU.
+ *   irp[n+1], icol[nnz]: device int32; val[nnz]: device, of type val_type.
+ *   plan_work: device, at least spmv_plan_workspace_bytes(n, nnz) bytes,
+ *     owned by the caller, used by the plan until spmv_plan_destroy.
+ * The CRS contract is checked on the GPU: irp[0] = 0, irp[n] = nnz, irp
+ * non-decreasing, 0 <= icol[p] < n; rows may be empty, unsorted or hold
+ * duplicates.  Violations return SPMV_E_MATRIX (no plan is made).
+ * Synchronises `stream` once to read the statistics back: on return they are
+ * final.  The plan's memory limit for transformed formats starts at
+ * 8 x the CRS bytes (spmv_plan_set_limit changes it). */
+spmv_status spmv_plan_create(spmv_plan **plan, int32_t n, int64_t nnz,
+                             const int32_t *irp, const int32_t *icol, const void *val,
+                             spmv_dtype val_type, void *plan_work, size_t plan_work_bytes,
+                             void *stream);
+
+/* Host only.  Copies the statistics out. */
+spmv_status spmv_plan_stats(const spmv_plan *p, spmv_stats *out);
+
+/* Host only.  Largest number of bytes one transformed format (its output
+ * arrays) may take; a transformation past it returns SPMV_E_TOO_LARGE
+ * before any device work.  This is the memory guard of section 4.2, where
+ * ELL overflowed memory for torso1. */
+spmv_status spmv_plan_set_limit(spmv_plan *p, size_t max_format_bytes);
+
+/* Host only.  Output and workspace sizes of the transformation into `f`
+ * (COO_ROW, CCS, COO_COL, ELL_ROW, ELL_COL).  ELL_COL needs csr_to_ccs to
+ * have run (its width is the longest column): SPMV_E_NOT_READY before.
+ * SPMV_E_TOO_LARGE when the format exceeds the plan's limit (sizes are still
+ * filled in). */
+spmv_status spmv_buffer_sizes(const spmv_plan *p, spmv_format f, spmv_sizes *out);
+
+/* ------------------------------------------------------- transformations */
+
+/* CRS -> COO (section 2.1).  column_wise = 0: COO-Row, out->ptr[0] =
+ * irow[nnz] with irow[p] = the row owning position p (VAL and ICOL are the
+ * CRS arrays).  column_wise = 1: COO-Column (Phase II), out->ptr[0] =
+ * jcol[nnz] with jcol[q] = the column owning CCS position q; needs
+ * csr_to_ccs first (SPMV_E_NOT_READY).  work: unused (may be NULL).
+ * Index arrays are bit-exact with the definition. */
+spmv_status csr_to_coo(spmv_plan *p, int column_wise, const spmv_buffers *out,
+                       void *work, size_t work_bytes, void *stream);
+
+/* CRS -> CCS, Phase I of section 2.1: column pointers ccp[n+1] (exclusive
+ * prefix of the column counts, ccp[n] = nnz), row numbers irow_t[nnz] and
+ * values val_t[nnz] in the stable order of the paper's counting sort:
+ * inside a column, by row, then by position within the row.  Bit-exact and
+ * deterministic.  work: device scratch of spmv_sizes.workspace bytes.
+ * Out-of-place: the CRS arrays are not modified.  Synchronises `stream`
+ * once (after the column count) to size the column sort and to learn the
+ * longest column. */
+spmv_status csr_to_ccs(spmv_plan *p, const spmv_buffers *out, void *work, size_t work_bytes,
+                       void *stream);
+
+/* CRS -> ELL (section 2.1).  column_wise = 0: ELL-Row from the CRS rows,
+ * width = longest row.  column_wise = 1: ELL-Column from the CCS columns
+ * (needs csr_to_ccs), width = longest column.  Slot k of line i sits at
+ * k*n + i; padding slots hold value +0.0 (all bits zero) and the line's own
+ * index i.  SPMV_E_TOO_LARGE if width*n overflows or the arrays exceed the
+ * plan's limit.  work: unused. */
+spmv_status csr_to_ell(spmv_plan *p, int column_wise, const spmv_buffers *out,
+                       void *work, size_t work_bytes, void *stream);
+
+/* ----------------------------------------------------------------- SpMV */
+
+/* y = A x (overwrites y; the paper's loops accumulate into a cleared Y) in
+ * format f (section 3, Figs. 1-3, and CRS itself).  x[n] and y[n] are
+ * device arrays: F64 for F64 values, else F32 (accumulation in F32).
+ * variant (CRS only): 0 one thread per row; 1 a power-of-two group of
+ * lanes per row sized from the mean row length; 2..7 a group of
+ * 2^(variant-1) lanes.  Other formats take variant 0.
+ * Determinism: CRS, COO_ROW and ELL_ROW are deterministic run to run;
+ * COO_COL and ELL_COL scatter with atomics and are not.  x and y must not
+ * overlap.  SPMV_E_NOT_READY when the format has not been built. */
+spmv_status spmv_exec(const spmv_plan *p, spmv_format f, int variant,
+                      const void *x, void *y, void *stream);
+
+/* ---------------------------------------------------------- auto-tuning */
+
+/* Host only.  Off-line phase step (4) of section 2.2: from m benchmark points
+ * (d[i] = D_mat, r[i] = R_ell, feasible[i] = 0 when the format did not fit in
+ * memory, which drops the point), D* is the smallest D_mat among feasible
+ * points with R_ell < c (+inf when there is none).  Fills c and d_star and
+ * clears the cost model. */
+spmv_status at_table_build(const double *d, const double *r, const int32_t *feasible,
+                           int32_t m, double c, at_table *out);
+
+/* Host only.  On-line phase of section 2.2.  k_repeats <= 0: the paper's
+ * rule, ELL_ROW when D_mat < D* and ELL-Row fits the plan's limit, else
+ * CRS (variant 0).  k_repeats > 0 and a calibrated table: the option with
+ * the least estimated transformation + k_repeats SpMVs among CRS (both
+ * variants), COO_ROW and ELL_ROW (when it fits); ties keep CRS. */
+spmv_status at_choose_format(const spmv_plan *p, const at_table *t, int64_t k_repeats,
+                             spmv_format *fmt, int *variant, at_decision *why);
+
+/* Host only.  The same decision from statistics alone: `st` as filled by
+ * spmv_plan_stats, val_type the value storage and max_format_bytes the
+ * memory limit that the ELL-Row footprint is checked against. */
+spmv_status at_choose_format_stats(const spmv_stats *st, spmv_dtype val_type, size_t max_format_bytes,
+                                   const at_table *t, int64_t k_repeats,
+                                   spmv_format *fmt, int *variant, at_decision *why);
+
+/* ------------------------------------------------------------ utilities */
+
+/* Rounds m binary64 values to `to` (F32, BF16 or F16), to nearest with
+ * ties to even, straight from binary64; overflow gives +-inf.  in and out
+ * are device arrays. */
+spmv_status spmv_convert_values(const double *in, void *out, int64_t m, spmv_dtype to,
+                                void *stream);
+
+void spmv_plan_destroy(spmv_plan *p);
+const char *spmv_status_string(spmv_status s);
+const char *spmv_plan_last_error(const spmv_plan *p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPMVAT_H */

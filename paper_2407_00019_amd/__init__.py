@@ -1,0 +1,348 @@
+"""Python binding of libspmvat (include/spmvat.h): run-time CRS -> COO / CCS /
+ELL transformation, SpMV in every format, and the D_mat / R_ell auto-tuner of
+Katagiri & Sato (arXiv:2407.00019), on AMD MI355X.
+
+The functions below carry the C ABI's names and only marshal arguments:
+torch tensors become device pointers, torch's current stream becomes the
+hipStream_t.  Every step runs in the HIP library; if it is not built, loading
+raises (there is no fallback).  ``Plan`` is a convenience owner that
+allocates the caller-owned device buffers as torch tensors and keeps them
+alive as long as the plan.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import torch  # first: its HIP runtime is the one the library binds to
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libspmvat.so")
+_LIB = None
+
+# enums of spmvat.h
+SPMV_OK, SPMV_E_ARG, SPMV_E_MATRIX, SPMV_E_TOO_LARGE, SPMV_E_NOT_READY, SPMV_E_HIP = range(6)
+CRS, COO_ROW, CCS, COO_COL, ELL_ROW, ELL_COL = range(6)
+F64, F32, BF16, F16 = range(4)
+FORMAT_NAMES = {CRS: "crs", COO_ROW: "coo_row", CCS: "ccs", COO_COL: "coo_col", ELL_ROW: "ell_row",
+                ELL_COL: "ell_col"}
+DTYPE_OF_TORCH = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16}
+TORCH_OF_DTYPE = {v: k for k, v in DTYPE_OF_TORCH.items()}
+AT_DBUCKETS = 8
+
+
+class SpmvError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str = ""):
+        self.status = status
+        msg = f"{what}: {status_string(status)} ({status})"
+        if detail:
+            msg += f": {detail}"
+        super().__init__(msg)
+
+
+class spmv_stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("sum_len", ctypes.c_int64),
+                ("sum_len2", ctypes.c_int64), ("max_row", ctypes.c_int32), ("min_row", ctypes.c_int32),
+                ("max_col", ctypes.c_int32), ("mu", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("d_mat", ctypes.c_double)]
+
+
+class spmv_sizes(ctypes.Structure):
+    _fields_ = [("bytes", ctypes.c_size_t * 4), ("workspace", ctypes.c_size_t), ("width", ctypes.c_int32)]
+
+
+class spmv_buffers(ctypes.Structure):
+    _fields_ = [("ptr", ctypes.c_void_p * 4), ("bytes", ctypes.c_size_t * 4)]
+
+
+class at_table(ctypes.Structure):
+    _fields_ = [("c", ctypes.c_double), ("d_star", ctypes.c_double), ("calibrated", ctypes.c_int32),
+                ("spmv_bps", ((ctypes.c_double * AT_DBUCKETS) * 2) * 6),
+                ("trans_bps", (ctypes.c_double * AT_DBUCKETS) * 6), ("launch_s", ctypes.c_double)]
+
+
+class at_decision(ctypes.Structure):
+    _fields_ = [("rule", ctypes.c_int32), ("feasible_ell", ctypes.c_int32), ("d_mat", ctypes.c_double),
+                ("t_crs_hat", ctypes.c_double), ("t_fmt_hat", ctypes.c_double),
+                ("t_trans_hat", ctypes.c_double), ("k_break_even", ctypes.c_double)]
+
+
+def build() -> None:
+    """Compile libspmvat.so for gfx950 in place (always recompiles)."""
+    subprocess.run(["make", "-B", "-s", "-j8", "-C", os.path.join(_HERE, "csrc")], check=True)
+
+
+def lib():
+    """The loaded library; raises when it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libspmvat.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, sz, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double
+        st = ctypes.c_int
+        L.spmv_plan_workspace_bytes.argtypes = [i32, i64]
+        L.spmv_plan_workspace_bytes.restype = sz
+        L.spmv_plan_create.argtypes = [ctypes.POINTER(P), i32, i64, P, P, P, ctypes.c_int, P, sz, P]
+        L.spmv_plan_create.restype = st
+        L.spmv_plan_stats.argtypes = [P, ctypes.POINTER(spmv_stats)]
+        L.spmv_plan_stats.restype = st
+        L.spmv_plan_set_limit.argtypes = [P, sz]
+        L.spmv_plan_set_limit.restype = st
+        L.spmv_buffer_sizes.argtypes = [P, ctypes.c_int, ctypes.POINTER(spmv_sizes)]
+        L.spmv_buffer_sizes.restype = st
+        for name in ("csr_to_coo", "csr_to_ell"):
+            fn = getattr(L, name)
+            fn.argtypes = [P, ctypes.c_int, ctypes.POINTER(spmv_buffers), P, sz, P]
+            fn.restype = st
+        L.csr_to_ccs.argtypes = [P, ctypes.POINTER(spmv_buffers), P, sz, P]
+        L.csr_to_ccs.restype = st
+        L.spmv_exec.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, P]
+        L.spmv_exec.restype = st
+        L.at_table_build.argtypes = [P, P, P, i32, f64, ctypes.POINTER(at_table)]
+        L.at_table_build.restype = st
+        L.at_choose_format.argtypes = [P, ctypes.POINTER(at_table), i64, ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(at_decision)]
+        L.at_choose_format.restype = st
+        L.at_choose_format_stats.argtypes = [ctypes.POINTER(spmv_stats), ctypes.c_int, sz, ctypes.POINTER(at_table),
+                                             i64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                             ctypes.POINTER(at_decision)]
+        L.at_choose_format_stats.restype = st
+        L.spmv_convert_values.argtypes = [P, P, i64, ctypes.c_int, P]
+        L.spmv_convert_values.restype = st
+        L.spmv_plan_destroy.argtypes = [P]
+        L.spmv_plan_destroy.restype = None
+        L.spmv_status_string.argtypes = [ctypes.c_int]
+        L.spmv_status_string.restype = ctypes.c_char_p
+        L.spmv_plan_last_error.argtypes = [P]
+        L.spmv_plan_last_error.restype = ctypes.c_char_p
+        _LIB = L
+    return _LIB
+
+
+# ------------------------------------------------------------- marshalling
+
+def _ptr(t) -> ctypes.c_void_p:
+    if t is None:
+        return ctypes.c_void_p(None)
+    if isinstance(t, int):
+        return ctypes.c_void_p(t)
+    return ctypes.c_void_p(t.data_ptr() if t.numel() > 0 else None)
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(stream)
+
+
+def _check(status: int, what: str, plan=None) -> None:
+    if status != SPMV_OK:
+        detail = ""
+        if plan is not None and status == SPMV_E_HIP:
+            detail = lib().spmv_plan_last_error(plan).decode()
+        raise SpmvError(status, what, detail)
+
+
+def status_string(s: int) -> str:
+    return lib().spmv_status_string(s).decode()
+
+
+def _buffers(tensors) -> spmv_buffers:
+    b = spmv_buffers()
+    for k, t in enumerate(tensors):
+        b.ptr[k] = _ptr(t).value
+        b.bytes[k] = t.numel() * t.element_size()
+    return b
+
+
+# --------------------------------------------------- the C ABI, by name
+
+def spmv_plan_workspace_bytes(n: int, nnz: int) -> int:
+    return int(lib().spmv_plan_workspace_bytes(n, nnz))
+
+
+def spmv_plan_create(n, nnz, irp, icol, val, val_type, plan_work, stream=None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    s = lib().spmv_plan_create(ctypes.byref(h), n, nnz, _ptr(irp), _ptr(icol), _ptr(val), val_type,
+                               _ptr(plan_work), plan_work.numel() * plan_work.element_size(), _stream(stream))
+    _check(s, "spmv_plan_create")
+    return h
+
+
+def spmv_plan_stats(plan) -> spmv_stats:
+    out = spmv_stats()
+    _check(lib().spmv_plan_stats(plan, ctypes.byref(out)), "spmv_plan_stats")
+    return out
+
+
+def spmv_plan_set_limit(plan, max_format_bytes: int) -> None:
+    _check(lib().spmv_plan_set_limit(plan, max_format_bytes), "spmv_plan_set_limit")
+
+
+def spmv_buffer_sizes(plan, fmt: int):
+    """(status, spmv_sizes): sizes are filled even for SPMV_E_TOO_LARGE."""
+    out = spmv_sizes()
+    s = lib().spmv_buffer_sizes(plan, fmt, ctypes.byref(out))
+    return s, out
+
+
+def csr_to_coo(plan, column_wise: int, out, work=None, stream=None) -> None:
+    b = _buffers(out)
+    wb = 0 if work is None else work.numel() * work.element_size()
+    _check(lib().csr_to_coo(plan, column_wise, ctypes.byref(b), _ptr(work), wb, _stream(stream)), "csr_to_coo", plan)
+
+
+def csr_to_ccs(plan, out, work, stream=None) -> None:
+    b = _buffers(out)
+    wb = work.numel() * work.element_size()
+    _check(lib().csr_to_ccs(plan, ctypes.byref(b), _ptr(work), wb, _stream(stream)), "csr_to_ccs", plan)
+
+
+def csr_to_ell(plan, column_wise: int, out, work=None, stream=None) -> None:
+    b = _buffers(out)
+    wb = 0 if work is None else work.numel() * work.element_size()
+    _check(lib().csr_to_ell(plan, column_wise, ctypes.byref(b), _ptr(work), wb, _stream(stream)), "csr_to_ell", plan)
+
+
+def spmv_exec(plan, fmt: int, variant: int, x, y, stream=None) -> None:
+    _check(lib().spmv_exec(plan, fmt, variant, _ptr(x), _ptr(y), _stream(stream)), "spmv_exec", plan)
+
+
+def at_table_build(d, r, feasible=None, c: float = 1.0) -> at_table:
+    m = len(d)
+    D = (ctypes.c_double * max(m, 1))(*d)
+    R = (ctypes.c_double * max(m, 1))(*r)
+    F = (ctypes.c_int32 * max(m, 1))(*(feasible if feasible is not None else [1] * m))
+    out = at_table()
+    _check(lib().at_table_build(D, R, F, m, c, ctypes.byref(out)), "at_table_build")
+    return out
+
+
+def at_choose_format(plan, table: at_table, k_repeats: int):
+    """(format, variant, at_decision)."""
+    f, v, why = ctypes.c_int(), ctypes.c_int(), at_decision()
+    _check(lib().at_choose_format(plan, ctypes.byref(table), k_repeats, ctypes.byref(f), ctypes.byref(v),
+                                  ctypes.byref(why)), "at_choose_format")
+    return f.value, v.value, why
+
+
+def at_choose_format_stats(stats: spmv_stats, val_type: int, max_format_bytes: int, table: at_table,
+                           k_repeats: int):
+    """(format, variant, at_decision) from statistics alone (host only)."""
+    f, v, why = ctypes.c_int(), ctypes.c_int(), at_decision()
+    _check(lib().at_choose_format_stats(ctypes.byref(stats), val_type, max_format_bytes, ctypes.byref(table),
+                                        k_repeats, ctypes.byref(f), ctypes.byref(v), ctypes.byref(why)),
+           "at_choose_format_stats")
+    return f.value, v.value, why
+
+
+def spmv_convert_values(inp, out, to: int, stream=None) -> None:
+    _check(lib().spmv_convert_values(_ptr(inp), _ptr(out), inp.numel(), to, _stream(stream)), "spmv_convert_values")
+
+
+def spmv_plan_destroy(plan) -> None:
+    lib().spmv_plan_destroy(plan)
+
+
+# ---------------------------------------------------------- convenience
+
+def convert_values(val64: torch.Tensor, to: int, stream=None) -> torch.Tensor:
+    """binary64 device values -> a new tensor of the storage type `to`."""
+    out = torch.empty(val64.numel(), dtype=TORCH_OF_DTYPE[to], device=val64.device)
+    spmv_convert_values(val64, out, to, stream)
+    return out
+
+
+class Plan:
+    """Owns a plan over device CRS arrays and the device buffers of every
+    format built on it (torch tensors, kept alive with the plan)."""
+
+    def __init__(self, irp: torch.Tensor, icol: torch.Tensor, val: torch.Tensor, stream=None):
+        assert irp.dtype == torch.int32 and icol.dtype == torch.int32
+        self.n = irp.numel() - 1
+        self.nnz = icol.numel()
+        self.dtype = DTYPE_OF_TORCH[val.dtype]
+        self.device = irp.device
+        self.crs = (irp, icol, val)
+        self.work = torch.empty(spmv_plan_workspace_bytes(self.n, self.nnz), dtype=torch.uint8, device=self.device)
+        self.handle = spmv_plan_create(self.n, self.nnz, irp, icol, val, self.dtype, self.work, stream)
+        self.buffers = {}
+        self.ccs_work = None
+
+    def __del__(self):
+        self.close()
+
+    def close(self) -> None:
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            spmv_plan_destroy(h)
+            self.handle = None
+
+    @property
+    def stats(self) -> spmv_stats:
+        return spmv_plan_stats(self.handle)
+
+    def set_limit(self, max_format_bytes: int) -> None:
+        spmv_plan_set_limit(self.handle, max_format_bytes)
+
+    def sizes(self, fmt: int):
+        return spmv_buffer_sizes(self.handle, fmt)
+
+    def _alloc(self, fmt: int):
+        s, sz = self.sizes(fmt)
+        _check(s, f"spmv_buffer_sizes({FORMAT_NAMES[fmt]})")
+        vt = TORCH_OF_DTYPE[self.dtype]
+        vb = torch.empty(0, dtype=vt).element_size()
+        dev = self.device
+        if fmt in (COO_ROW, COO_COL):
+            out = [torch.empty(sz.bytes[0] // 4, dtype=torch.int32, device=dev)]
+        elif fmt == CCS:
+            out = [torch.empty(sz.bytes[0] // 4, dtype=torch.int32, device=dev),
+                   torch.empty(sz.bytes[1] // 4, dtype=torch.int32, device=dev),
+                   torch.empty(sz.bytes[2] // vb, dtype=vt, device=dev)]
+        else:
+            out = [torch.empty(sz.bytes[0] // vb, dtype=vt, device=dev),
+                   torch.empty(sz.bytes[1] // 4, dtype=torch.int32, device=dev)]
+        work = torch.empty(sz.workspace, dtype=torch.uint8, device=dev) if sz.workspace else None
+        return out, work, sz
+
+    def to_coo(self, column_wise: bool = False, stream=None):
+        fmt = COO_COL if column_wise else COO_ROW
+        out, _, _ = self._alloc(fmt)
+        csr_to_coo(self.handle, int(column_wise), out, None, stream)
+        self.buffers[fmt] = out
+        return out
+
+    def to_ccs(self, stream=None):
+        out, work, _ = self._alloc(CCS)
+        csr_to_ccs(self.handle, out, work, stream)
+        self.buffers[CCS] = out
+        self.ccs_work = work
+        for f in (COO_COL, ELL_COL):
+            self.buffers.pop(f, None)
+        return out
+
+    def to_ell(self, column_wise: bool = False, stream=None):
+        fmt = ELL_COL if column_wise else ELL_ROW
+        out, _, sz = self._alloc(fmt)
+        csr_to_ell(self.handle, int(column_wise), out, None, stream)
+        self.buffers[fmt] = out
+        return out, sz.width
+
+    def release(self, fmt: int) -> None:
+        self.buffers.pop(fmt, None)
+
+    def spmv(self, fmt: int, x: torch.Tensor, y: torch.Tensor | None = None, variant: int = 0, stream=None):
+        if y is None:
+            y = torch.empty_like(x)
+        spmv_exec(self.handle, fmt, variant, x, y, stream)
+        return y
+
+    def choose(self, table: at_table, k_repeats: int = 0):
+        return at_choose_format(self.handle, table, k_repeats)
+

@@ -1,0 +1,501 @@
+// C ABI of libspmvat (include/spmvat.h): plans, transformations, SpMV
+// dispatch and the auto-tuner's host-side decisions (section 2.2).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/spmvat.h"
+#include "kernels.h"
+
+using namespace spmvat;
+
+#define SPMV_API extern "C" __attribute__((visibility("default")))
+
+struct spmv_plan {
+    int32_t n = 0;
+    int64_t nnz = 0;
+    spmv_dtype dt = SPMV_F64;
+    const int32_t* irp = nullptr;
+    const int32_t* icol = nullptr;
+    const void* val = nullptr;
+    char* work = nullptr;
+    size_t work_bytes = 0;
+    spmv_stats st{};
+    size_t limit = 0;
+    // formats built so far (borrowed caller buffers; arrays may be null when nnz = 0)
+    bool has_coo_row = false, has_ccs = false, has_coo_col = false;
+    const int32_t* irow = nullptr;                                            // COO-Row
+    const int32_t* ccp = nullptr; const int32_t* irow_t = nullptr; const void* val_t = nullptr;  // CCS
+    const int32_t* jcol = nullptr;                                            // COO-Col
+    int32_t ell_w = -1; const void* ell_val = nullptr; const int32_t* ell_col = nullptr;        // ELL-Row
+    int32_t ellc_w = -1; const void* ellc_val = nullptr; const int32_t* ellc_row = nullptr;     // ELL-Col
+    std::string err;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+inline int vbytes_of(spmv_dtype t) { return t == SPMV_F64 ? 8 : t == SPMV_F32 ? 4 : 2; }
+inline int xbytes_of(spmv_dtype t) { return t == SPMV_F64 ? 8 : 4; }
+inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+inline bool valid_dtype(int t) { return t >= SPMV_F64 && t <= SPMV_F16; }
+
+spmv_status hip_fail(const spmv_plan* p, hipError_t e) {
+    if (p) const_cast<spmv_plan*>(p)->err = hipGetErrorString(e);
+    return SPMV_E_HIP;
+}
+
+#define HIP_TRY(p, call)                                       \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return hip_fail((p), e_);        \
+    } while (0)
+
+// Plan workspace layout: [RowStats | COO carries].
+inline size_t plan_ws_bytes(int64_t nnz) {
+    return round_up(sizeof(RowStats), kAlign) + round_up(coo_carry_bytes(nnz), kAlign);
+}
+inline RowStats* plan_rowstats(const spmv_plan* p) { return reinterpret_cast<RowStats*>(p->work); }
+inline void* plan_carries(const spmv_plan* p) { return p->work + round_up(sizeof(RowStats), kAlign); }
+
+size_t crs_bytes(const spmv_plan* p) {
+    return (size_t)(p->n + 1) * 4 + (size_t)p->nnz * (4 + (size_t)vbytes_of(p->dt));
+}
+
+// CCS workspace layout.
+struct CcsWs {
+    size_t cursor, bsum, mid, lng, sum, keys, tmp, total;
+};
+CcsWs ccs_ws(int32_t n, int64_t nnz) {
+    CcsWs w{};
+    size_t o = 0;
+    w.cursor = o; o += round_up((size_t)n * 4, kAlign);
+    w.bsum = o;   o += round_up(col_scan_bsum_count(n) * 4, kAlign);
+    const size_t nmid = std::min<size_t>((size_t)n, (size_t)(nnz / (kSortSmall + 1)) + 1);
+    const size_t nlong = std::min<size_t>((size_t)n, (size_t)(nnz / (kSortMid + 1)) + 1);
+    w.mid = o;    o += round_up(nmid * 4, kAlign);
+    w.lng = o;    o += round_up(nlong * 4, kAlign);
+    w.sum = o;    o += round_up(sizeof(ColSummary), kAlign);
+    w.keys = o;   o += round_up((size_t)nnz * 8, kAlign);
+    w.tmp = o;    o += round_up((size_t)std::min<int64_t>(n, nnz) * 8, kAlign);
+    w.total = o;
+    return w;
+}
+
+bool check_buffers(const spmv_buffers* out, int count, const spmv_sizes& need) {
+    if (!out) return false;
+    for (int k = 0; k < count; ++k) {
+        if (need.bytes[k] == 0) continue;
+        if (!out->ptr[k] || !aligned16(out->ptr[k]) || out->bytes[k] < need.bytes[k]) return false;
+    }
+    return true;
+}
+
+int auto_vector_width(const spmv_plan* p) {
+    // smallest power of two covering the mean row length, within [2, 64]
+    int w = 2;
+    while (w < 64 && (double)w < p->st.mu) w <<= 1;
+    return w;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ plan
+
+SPMV_API size_t spmv_plan_workspace_bytes(int32_t n, int64_t nnz) {
+    (void)n;
+    return plan_ws_bytes(nnz < 0 ? 0 : nnz);
+}
+
+SPMV_API spmv_status spmv_plan_create(spmv_plan** plan, int32_t n, int64_t nnz, const int32_t* irp,
+                                      const int32_t* icol, const void* val, spmv_dtype val_type,
+                                      void* plan_work, size_t plan_work_bytes, void* stream) {
+    if (!plan) return SPMV_E_ARG;
+    *plan = nullptr;
+    if (n < 1 || nnz < 0 || nnz > INT32_MAX || !valid_dtype(val_type)) return SPMV_E_ARG;
+    if (!irp || !plan_work || (nnz > 0 && (!icol || !val))) return SPMV_E_ARG;
+    if (!aligned16(irp) || !aligned16(icol) || !aligned16(val) || !aligned16(plan_work)) return SPMV_E_ARG;
+    if (plan_work_bytes < plan_ws_bytes(nnz)) return SPMV_E_ARG;
+    spmv_plan* p = new (std::nothrow) spmv_plan();
+    if (!p) return SPMV_E_ARG;
+    p->n = n; p->nnz = nnz; p->dt = val_type;
+    p->irp = irp; p->icol = icol; p->val = val;
+    p->work = static_cast<char*>(plan_work); p->work_bytes = plan_work_bytes;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    RowStats rs{};
+    hipError_t e = launch_row_stats(n, nnz, irp, icol, plan_rowstats(p), s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&rs, plan_rowstats(p), sizeof(rs), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { delete p; return SPMV_E_HIP; }
+    if (rs.flags != 0) { delete p; return SPMV_E_MATRIX; }
+    spmv_stats& st = p->st;
+    st.n = n; st.nnz = nnz;
+    st.sum_len = (int64_t)rs.s1; st.sum_len2 = (int64_t)rs.s2;
+    st.max_row = rs.max_len; st.min_row = (int32_t)rs.min_len; st.max_col = -1;
+    // Eq. (4) from the exact integer moments: num = n*s2 - s1^2 (= n^2 sigma^2),
+    // rounded once; sigma = sqrt(num)/n, D_mat = sqrt(num)/s1.
+    const unsigned __int128 num = (unsigned __int128)(uint64_t)n * (uint64_t)rs.s2 -
+                                  (unsigned __int128)rs.s1 * (unsigned __int128)rs.s1;
+    uint64_t hi = (uint64_t)(num >> 64), lo = (uint64_t)num;
+    double numd;
+    {
+        // nearest binary64 (ties to even) of the 128-bit integer, written with
+        // 64-bit halves: the top 64 significant bits carry the rounding, the
+        // bits below them only stick
+        if (hi == 0) {
+            numd = (double)lo;  // the hardware conversion rounds to nearest even
+        } else {
+            int lz = __builtin_clzll(hi);
+            int sh = 64 - lz;                         // bits of num beyond the low 64
+            uint64_t top = (hi << lz) | (lz ? (lo >> (64 - lz)) : 0);   // top 64 bits
+            uint64_t rest = lz ? (lo << lz) : lo;                        // bits shifted out
+            top |= (rest != 0) ? 1u : 0u;            // sticky below the 64 kept bits
+            numd = std::ldexp((double)top, sh);      // one rounding of 64 -> 53 bits
+        }
+    }
+    const double r = std::sqrt(numd);
+    st.mu = (double)rs.s1 / (double)n;
+    st.sigma = r / (double)n;
+    st.d_mat = rs.s1 == 0 ? 0.0 : r / (double)rs.s1;
+    p->limit = 8 * crs_bytes(p);
+    *plan = p;
+    return SPMV_OK;
+}
+
+SPMV_API spmv_status spmv_plan_stats(const spmv_plan* p, spmv_stats* out) {
+    if (!p || !out) return SPMV_E_ARG;
+    *out = p->st;
+    return SPMV_OK;
+}
+
+SPMV_API spmv_status spmv_plan_set_limit(spmv_plan* p, size_t max_format_bytes) {
+    if (!p) return SPMV_E_ARG;
+    p->limit = max_format_bytes;
+    return SPMV_OK;
+}
+
+SPMV_API void spmv_plan_destroy(spmv_plan* p) { delete p; }
+
+SPMV_API const char* spmv_status_string(spmv_status s) {
+    switch (s) {
+        case SPMV_OK: return "ok";
+        case SPMV_E_ARG: return "invalid argument";
+        case SPMV_E_MATRIX: return "matrix breaks the CRS contract";
+        case SPMV_E_TOO_LARGE: return "format exceeds the memory limit";
+        case SPMV_E_NOT_READY: return "format not built";
+        case SPMV_E_HIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+SPMV_API const char* spmv_plan_last_error(const spmv_plan* p) { return p ? p->err.c_str() : ""; }
+
+// ------------------------------------------------------------------ sizes
+
+SPMV_API spmv_status spmv_buffer_sizes(const spmv_plan* p, spmv_format f, spmv_sizes* out) {
+    if (!p || !out) return SPMV_E_ARG;
+    std::memset(out, 0, sizeof(*out));
+    const size_t nnz = (size_t)p->nnz, n = (size_t)p->n, vb = (size_t)vbytes_of(p->dt);
+    switch (f) {
+        case SPMV_COO_ROW:
+            out->bytes[0] = nnz * 4;
+            return SPMV_OK;
+        case SPMV_CCS:
+            out->bytes[0] = (n + 1) * 4;
+            out->bytes[1] = nnz * 4;
+            out->bytes[2] = nnz * vb;
+            out->workspace = ccs_ws(p->n, p->nnz).total;
+            return SPMV_OK;
+        case SPMV_COO_COL:
+            out->bytes[0] = nnz * 4;
+            return SPMV_OK;
+        case SPMV_ELL_ROW:
+        case SPMV_ELL_COL: {
+            int32_t w = f == SPMV_ELL_ROW ? p->st.max_row : p->st.max_col;
+            if (w < 0) return SPMV_E_NOT_READY;
+            out->width = w;
+            const unsigned __int128 slots = (unsigned __int128)w * n;
+            if (slots > (unsigned __int128)(SIZE_MAX / 16)) return SPMV_E_TOO_LARGE;
+            out->bytes[0] = (size_t)slots * vb;
+            out->bytes[1] = (size_t)slots * 4;
+            if (out->bytes[0] + out->bytes[1] > p->limit) return SPMV_E_TOO_LARGE;
+            return SPMV_OK;
+        }
+        default:
+            return SPMV_E_ARG;
+    }
+}
+
+// ------------------------------------------------------- transformations
+
+SPMV_API spmv_status csr_to_coo(spmv_plan* p, int column_wise, const spmv_buffers* out, void* work,
+                                size_t work_bytes, void* stream) {
+    (void)work; (void)work_bytes;
+    if (!p) return SPMV_E_ARG;
+    spmv_sizes need;
+    spmv_status st = spmv_buffer_sizes(p, column_wise ? SPMV_COO_COL : SPMV_COO_ROW, &need);
+    if (st != SPMV_OK) return st;
+    if (column_wise && !p->has_ccs) return SPMV_E_NOT_READY;
+    if (!check_buffers(out, 1, need)) return SPMV_E_ARG;
+    if (need.bytes[0] > p->limit) return SPMV_E_TOO_LARGE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int32_t* dst = static_cast<int32_t*>(out->ptr[0]);
+    if (p->nnz > 0) HIP_TRY(p, launch_expand_ptr(p->n, column_wise ? p->ccp : p->irp, dst, s));
+    if (column_wise) { p->jcol = dst; p->has_coo_col = true; }
+    else { p->irow = dst; p->has_coo_row = true; }
+    return SPMV_OK;
+}
+
+SPMV_API spmv_status csr_to_ccs(spmv_plan* p, const spmv_buffers* out, void* work, size_t work_bytes,
+                                void* stream) {
+    if (!p) return SPMV_E_ARG;
+    spmv_sizes need;
+    spmv_status st = spmv_buffer_sizes(p, SPMV_CCS, &need);
+    if (st != SPMV_OK) return st;
+    if (!check_buffers(out, 3, need)) return SPMV_E_ARG;
+    if (need.bytes[0] + need.bytes[1] + need.bytes[2] > p->limit) return SPMV_E_TOO_LARGE;
+    if (!work || !aligned16(work) || work_bytes < need.workspace) return SPMV_E_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const CcsWs w = ccs_ws(p->n, p->nnz);
+    char* base = static_cast<char*>(work);
+    int32_t* cursor = reinterpret_cast<int32_t*>(base + w.cursor);
+    int32_t* bsum = reinterpret_cast<int32_t*>(base + w.bsum);
+    int32_t* mid = reinterpret_cast<int32_t*>(base + w.mid);
+    int32_t* lng = reinterpret_cast<int32_t*>(base + w.lng);
+    ColSummary* dsum = reinterpret_cast<ColSummary*>(base + w.sum);
+    unsigned long long* keys = reinterpret_cast<unsigned long long*>(base + w.keys);
+    unsigned long long* tmp = reinterpret_cast<unsigned long long*>(base + w.tmp);
+    int32_t* ccp = static_cast<int32_t*>(out->ptr[0]);
+    int32_t* irow_t = static_cast<int32_t*>(out->ptr[1]);
+    void* val_t = out->ptr[2];
+    const int vb = vbytes_of(p->dt);
+
+    // (1) column counts, (2) exclusive scan -> ccp and cursors
+    HIP_TRY(p, hipMemsetAsync(cursor, 0, (size_t)p->n * 4, s));
+    if (p->nnz > 0) HIP_TRY(p, launch_col_count(p->nnz, p->icol, cursor, s));
+    HIP_TRY(p, launch_col_scan(p->n, cursor, ccp, cursor, bsum, mid, lng, dsum, s));
+    ColSummary cs{};
+    HIP_TRY(p, hipMemcpyAsync(&cs, dsum, sizeof(cs), hipMemcpyDeviceToHost, s));
+    HIP_TRY(p, hipStreamSynchronize(s));
+    if ((int64_t)cs.total != p->nnz) {
+        p->err = "column counts do not add up to nnz";
+        return SPMV_E_HIP;
+    }
+    if (p->nnz > 0) {
+        // (3) scatter of packed (position, row) keys, (4) per-column sort + emit
+        HIP_TRY(p, launch_ccs_scatter(p->n, p->irp, p->icol, cursor, keys, s));
+        HIP_TRY(p, launch_ccs_sort_small(p->n, ccp, keys, p->val, vb, irow_t, val_t, s));
+        HIP_TRY(p, launch_ccs_sort_mid(cs.n_mid, mid, ccp, keys, p->val, vb, irow_t, val_t, s));
+        if (cs.n_long > 0) {
+            std::vector<int32_t> cols((size_t)cs.n_long);
+            HIP_TRY(p, hipMemcpyAsync(cols.data(), lng, cols.size() * 4, hipMemcpyDeviceToHost, s));
+            HIP_TRY(p, hipStreamSynchronize(s));
+            for (int32_t j : cols) {
+                int32_t se[2];
+                HIP_TRY(p, hipMemcpyAsync(se, ccp + j, 8, hipMemcpyDeviceToHost, s));
+                HIP_TRY(p, hipStreamSynchronize(s));
+                const int32_t len = se[1] - se[0];
+                // the merge passes need len keys of scratch; longer columns (only
+                // possible with duplicate entries) rank without scratch
+                const size_t cap = (size_t)std::min<int64_t>(p->n, p->nnz);
+                HIP_TRY(p, launch_ccs_sort_long(se[0], len, keys, (size_t)len <= cap ? tmp : nullptr, p->val, vb,
+                                                irow_t, val_t, s));
+            }
+        }
+    }
+    p->ccp = ccp; p->irow_t = irow_t; p->val_t = val_t; p->has_ccs = true;
+    p->st.max_col = cs.max_len;
+    p->jcol = nullptr; p->has_coo_col = false;   // a rebuilt CCS invalidates the formats built on it
+    p->ellc_w = -1; p->ellc_val = nullptr; p->ellc_row = nullptr;
+    return SPMV_OK;
+}
+
+SPMV_API spmv_status csr_to_ell(spmv_plan* p, int column_wise, const spmv_buffers* out, void* work,
+                                size_t work_bytes, void* stream) {
+    (void)work; (void)work_bytes;
+    if (!p) return SPMV_E_ARG;
+    if (column_wise && !p->has_ccs) return SPMV_E_NOT_READY;
+    spmv_sizes need;
+    spmv_status st = spmv_buffer_sizes(p, column_wise ? SPMV_ELL_COL : SPMV_ELL_ROW, &need);
+    if (st != SPMV_OK) return st;
+    if (!check_buffers(out, 2, need)) return SPMV_E_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int vb = vbytes_of(p->dt);
+    if (column_wise) {
+        HIP_TRY(p, launch_ell_pack(p->n, need.width, p->ccp, p->irow_t, p->val_t, vb, out->ptr[0],
+                                   static_cast<int32_t*>(out->ptr[1]), s));
+        p->ellc_w = need.width; p->ellc_val = out->ptr[0]; p->ellc_row = static_cast<int32_t*>(out->ptr[1]);
+    } else {
+        HIP_TRY(p, launch_ell_pack(p->n, need.width, p->irp, p->icol, p->val, vb, out->ptr[0],
+                                   static_cast<int32_t*>(out->ptr[1]), s));
+        p->ell_w = need.width; p->ell_val = out->ptr[0]; p->ell_col = static_cast<int32_t*>(out->ptr[1]);
+    }
+    return SPMV_OK;
+}
+
+// ------------------------------------------------------------------ SpMV
+
+SPMV_API spmv_status spmv_exec(const spmv_plan* p, spmv_format f, int variant, const void* x, void* y,
+                               void* stream) {
+    if (!p || !x || !y || !aligned16(x) || !aligned16(y)) return SPMV_E_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int dt = (int)p->dt;
+    const int64_t ybytes = (int64_t)p->n * xbytes_of(p->dt);
+    switch (f) {
+        case SPMV_CRS:
+            if (variant < 0 || variant > 7) return SPMV_E_ARG;
+            if (variant == 0) HIP_TRY(p, launch_spmv_crs_scalar(dt, p->n, p->irp, p->icol, p->val, x, y, s));
+            else {
+                const int w = variant == 1 ? auto_vector_width(p) : (1 << (variant - 1));
+                HIP_TRY(p, launch_spmv_crs_vector(dt, w, p->n, p->irp, p->icol, p->val, x, y, s));
+            }
+            return SPMV_OK;
+        case SPMV_COO_ROW:
+            if (variant != 0) return SPMV_E_ARG;
+            if (!p->has_coo_row) return SPMV_E_NOT_READY;
+            if (p->st.min_row == 0 || p->nnz == 0) HIP_TRY(p, launch_fill_zero(y, ybytes, s));
+            HIP_TRY(p, launch_spmv_coo_row(dt, p->n, p->nnz, p->irow, p->icol, p->val, x, y, plan_carries(p), s));
+            return SPMV_OK;
+        case SPMV_ELL_ROW:
+            if (variant != 0) return SPMV_E_ARG;
+            if (p->ell_w < 0) return SPMV_E_NOT_READY;
+            HIP_TRY(p, launch_spmv_ell_row(dt, p->n, p->ell_w, p->ell_val, p->ell_col, x, y, s));
+            return SPMV_OK;
+        case SPMV_ELL_COL:
+            if (variant != 0) return SPMV_E_ARG;
+            if (p->ellc_w < 0) return SPMV_E_NOT_READY;
+            HIP_TRY(p, launch_spmv_ell_col(dt, p->n, p->ellc_w, p->ellc_val, p->ellc_row, x, y, s));
+            return SPMV_OK;
+        case SPMV_COO_COL:
+            if (variant != 0) return SPMV_E_ARG;
+            if (!p->has_coo_col || !p->has_ccs) return SPMV_E_NOT_READY;
+            HIP_TRY(p, launch_fill_zero(y, ybytes, s));
+            if (p->nnz > 0)
+                HIP_TRY(p, launch_spmv_coo_col(dt, p->nnz, p->jcol, p->irow_t, p->val_t, x, y, s));
+            return SPMV_OK;
+        case SPMV_CCS:
+            return SPMV_E_ARG;   // CCS is an intermediate form; SpMV uses COO_COL or ELL_COL
+        default:
+            return SPMV_E_ARG;
+    }
+}
+
+// ----------------------------------------------------------- conversion
+
+SPMV_API spmv_status spmv_convert_values(const double* in, void* out, int64_t m, spmv_dtype to, void* stream) {
+    if (m < 0 || (to != SPMV_F32 && to != SPMV_BF16 && to != SPMV_F16)) return SPMV_E_ARG;
+    if (m == 0) return SPMV_OK;
+    if (!in || !out || !aligned16(in) || !aligned16(out)) return SPMV_E_ARG;
+    hipError_t e = launch_convert((int)to, m, in, out, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SPMV_OK : SPMV_E_HIP;
+}
+
+// ----------------------------------------------------------- auto-tuning
+
+SPMV_API spmv_status at_table_build(const double* d, const double* r, const int32_t* feasible, int32_t m,
+                                    double c, at_table* out) {
+    if (!out || m < 0 || (m > 0 && (!d || !r))) return SPMV_E_ARG;
+    std::memset(out, 0, sizeof(*out));
+    out->c = c;
+    // D* = the smallest D_mat among feasible points whose R_ell falls below c
+    double dstar = std::numeric_limits<double>::infinity();
+    for (int32_t i = 0; i < m; ++i) {
+        if (feasible && !feasible[i]) continue;
+        if (!(r[i] >= c) && d[i] < dstar) dstar = d[i];
+    }
+    out->d_star = dstar;
+    return SPMV_OK;
+}
+
+namespace {
+
+int dbucket(double d) {
+    if (!(d >= 0)) return 0;
+    int b = (int)std::floor(d / 0.5);
+    return b < 0 ? 0 : (b >= AT_DBUCKETS ? AT_DBUCKETS - 1 : b);
+}
+
+// Algorithmic bytes of one SpMV in a format (x and y counted once, ELL
+// padding included) and of the transformation into it.
+double spmv_bytes(const spmv_stats& st, spmv_dtype dt, spmv_format f) {
+    const double n = st.n, nnz = (double)st.nnz, vb = vbytes_of(dt), xb = xbytes_of(dt);
+    switch (f) {
+        case SPMV_CRS: return (vb + 4) * nnz + 4 * (n + 1) + 2 * xb * n;
+        case SPMV_COO_ROW: return (vb + 8) * nnz + 2 * xb * n;
+        case SPMV_ELL_ROW: return (vb + 4) * n * (double)st.max_row + 2 * xb * n;
+        default: return 0;
+    }
+}
+double trans_bytes(const spmv_stats& st, spmv_dtype dt, spmv_format f) {
+    const double n = st.n, nnz = (double)st.nnz, vb = vbytes_of(dt);
+    switch (f) {
+        case SPMV_COO_ROW: return 4 * (n + 1) + 4 * nnz;
+        case SPMV_ELL_ROW: return (vb + 4) * nnz + 4 * (n + 1) + (vb + 4) * n * (double)st.max_row;
+        default: return 0;
+    }
+}
+
+// ELL-Row footprint check of spmv_buffer_sizes, from statistics.
+bool ell_row_fits(const spmv_stats& st, spmv_dtype dt, size_t limit) {
+    const unsigned __int128 slots = (unsigned __int128)(st.max_row < 0 ? 0 : st.max_row) * (uint64_t)st.n;
+    if (slots > (unsigned __int128)(SIZE_MAX / 16)) return false;
+    return (size_t)slots * (size_t)(vbytes_of(dt) + 4) <= limit;
+}
+
+}  // namespace
+
+SPMV_API spmv_status at_choose_format_stats(const spmv_stats* st, spmv_dtype dt, size_t limit,
+                                            const at_table* t, int64_t k_repeats, spmv_format* fmt,
+                                            int* variant, at_decision* why) {
+    if (!st || !t || !fmt || !variant || !valid_dtype(dt) || st->n < 1) return SPMV_E_ARG;
+    at_decision d{};
+    d.d_mat = st->d_mat;
+    d.feasible_ell = ell_row_fits(*st, dt, limit) ? 1 : 0;
+    if (k_repeats <= 0 || !t->calibrated) {
+        // the paper's on-line phase: ELL when D_mat < D*
+        d.rule = 0;
+        if (d.feasible_ell && st->d_mat < t->d_star) { *fmt = SPMV_ELL_ROW; *variant = 0; }
+        else { *fmt = SPMV_CRS; *variant = 0; }
+    } else {
+        // least estimated transformation + k SpMVs; ties keep CRS
+        d.rule = 1;
+        const int b = dbucket(st->d_mat);
+        const double k = (double)k_repeats;
+        auto est = [&](double bytes, double bps, int launches) {
+            return bps > 0 ? bytes / bps + launches * t->launch_s : std::numeric_limits<double>::infinity();
+        };
+        const double tc0 = est(spmv_bytes(*st, dt, SPMV_CRS), t->spmv_bps[SPMV_CRS][0][b], 1);
+        const double tc1 = est(spmv_bytes(*st, dt, SPMV_CRS), t->spmv_bps[SPMV_CRS][1][b], 1);
+        spmv_format bf = SPMV_CRS;
+        int bv = tc1 < tc0 ? 1 : 0;
+        const double tcrs = std::min(tc0, tc1);
+        double best = k * tcrs, bt = tcrs, btr = 0;
+        const spmv_format cands[2] = {SPMV_COO_ROW, SPMV_ELL_ROW};
+        for (spmv_format f : cands) {
+            if (f == SPMV_ELL_ROW && !d.feasible_ell) continue;
+            const double ts = est(spmv_bytes(*st, dt, f), t->spmv_bps[f][0][b], f == SPMV_COO_ROW ? 2 : 1);
+            const double tr = est(trans_bytes(*st, dt, f), t->trans_bps[f][b], 1);
+            const double cost = tr + k * ts;
+            if (cost < best) { best = cost; bf = f; bv = 0; bt = ts; btr = tr; }
+        }
+        *fmt = bf; *variant = bv;
+        d.t_crs_hat = tcrs; d.t_fmt_hat = bt; d.t_trans_hat = btr;
+        if (bf != SPMV_CRS && bt < tcrs) d.k_break_even = (btr / tcrs) / (1.0 - bt / tcrs);
+    }
+    if (why) *why = d;
+    return SPMV_OK;
+}
+
+SPMV_API spmv_status at_choose_format(const spmv_plan* p, const at_table* t, int64_t k_repeats, spmv_format* fmt,
+                                      int* variant, at_decision* why) {
+    if (!p) return SPMV_E_ARG;
+    return at_choose_format_stats(&p->st, p->dt, p->limit, t, k_repeats, fmt, variant, why);
+}

@@ -1,0 +1,61 @@
+// Device-side helpers shared by the spmvat kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spmvat {
+
+constexpr int kBlock = 256;   // threads per workgroup: 4 waves of 64
+constexpr int kWave = 64;
+constexpr int kXcds = 8;      // MI355X: 8 XCDs, each with its own 4 MB L2
+
+// Workgroups are dispatched round-robin over the XCDs (hardware block b runs
+// on XCD b % 8).  Renumbering so that each XCD receives one contiguous range
+// of logical blocks keeps neighbouring rows -- and the x entries they gather --
+// inside one XCD's L2.  A bijection on [0, nblocks).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nblocks) {
+    uint32_t per = nblocks / kXcds, rem = nblocks % kXcds;
+    uint32_t xcd = b % kXcds, idx = b / kXcds;
+    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+// Value storage types.  F64 values pair with F64 x/y; the reduced formats
+// pair with F32 x/y and F32 accumulation.
+struct bf16_t { uint16_t bits; };
+struct f16_t { uint16_t bits; };
+
+template <typename V> struct acc_of { using type = float; };
+template <> struct acc_of<double> { using type = double; };
+
+__device__ __forceinline__ double widen(double v) { return v; }
+__device__ __forceinline__ float widen(float v) { return v; }
+__device__ __forceinline__ float widen(bf16_t v) { return __uint_as_float((uint32_t)v.bits << 16); }
+__device__ __forceinline__ float widen(f16_t v) {
+    _Float16 h;
+    __builtin_memcpy(&h, &v.bits, 2);
+    return (float)h;
+}
+
+// Raw element types used when values are only moved (transformations).
+template <int B> struct raw_of;
+template <> struct raw_of<8> { using type = uint64_t; };
+template <> struct raw_of<4> { using type = uint32_t; };
+template <> struct raw_of<2> { using type = uint16_t; };
+
+// Largest r in [lo, hi] with a[r] <= q, for a non-decreasing a with a[lo] <= q.
+__device__ __forceinline__ int last_le(const int* a, int lo, int hi, int q) {
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (a[mid] <= q) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+}  // namespace spmvat

@@ -1,0 +1,310 @@
+// SpMV y = A x in every format of the method (section 3 and the CRS
+// baseline), templated over the value storage type V and the vector /
+// accumulator type X (double for double values, float otherwise).
+//
+//  CRS scalar     one thread per row (the plain CRS loop).
+//  CRS vector     a power-of-two lane group per row, coalesced row loads,
+//                 butterfly reduction inside the group.
+//  ELL-Row        Fig. 3: thread per row, slot loop inside, slot-major loads
+//                 coalesced across the wave; no reduction step.
+//  ELL-Column     thread per column, y(row) += val * x(col) with atomics.
+//  COO-Row        Fig. 2's entry-chunk partition as a segmented reduction:
+//                 8 consecutive entries per thread, a segmented scan across
+//                 the workgroup, workgroup carries folded in by a second
+//                 kernel in workgroup order -- deterministic.
+//  COO-Column     Fig. 1: entries in column order, y(row) += ... with atomics.
+#include "common.h"
+#include "kernels.h"
+
+namespace spmvat {
+
+template <typename X>
+__device__ __forceinline__ void atomic_add(X* p, X v) { unsafeAtomicAdd(p, v); }
+
+// ------------------------------------------------------------- CRS
+
+template <typename V, typename X>
+__global__ void __launch_bounds__(kBlock)
+k_spmv_crs_scalar(int n, const int* __restrict__ irp, const int* __restrict__ icol, const V* __restrict__ val,
+                  const X* __restrict__ x, X* __restrict__ y) {
+    const int i = (int)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int a = irp[i], b = irp[i + 1];
+    X s = 0;
+    for (int p = a; p < b; ++p) s += (X)widen(val[p]) * x[icol[p]];
+    y[i] = s;
+}
+
+template <typename V, typename X, int W>
+__global__ void __launch_bounds__(kBlock)
+k_spmv_crs_vector(int n, const int* __restrict__ irp, const int* __restrict__ icol, const V* __restrict__ val,
+                  const X* __restrict__ x, X* __restrict__ y) {
+    constexpr int kRows = kBlock / W;
+    const int row = (int)xcd_block(blockIdx.x, gridDim.x) * kRows + (int)threadIdx.x / W;
+    const int lane = threadIdx.x % W;
+    X s = 0;
+    if (row < n) {
+        const int a = irp[row], b = irp[row + 1];
+        for (int p = a + lane; p < b; p += W) s += (X)widen(val[p]) * x[icol[p]];
+    }
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1) s += __shfl_down(s, off, W);
+    if (lane == 0 && row < n) y[row] = s;
+}
+
+// ------------------------------------------------------------- ELL
+
+template <typename V, typename X>
+__global__ void __launch_bounds__(kBlock)
+k_spmv_ell_row(int n, int width, const V* __restrict__ ev, const int* __restrict__ ec, const X* __restrict__ x,
+               X* __restrict__ y) {
+    const int i = (int)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    X s = 0;
+    size_t off = (size_t)i;
+#pragma unroll 4
+    for (int k = 0; k < width; ++k, off += (size_t)n) s += (X)widen(ev[off]) * x[ec[off]];
+    y[i] = s;
+}
+
+template <typename V, typename X>
+__global__ void __launch_bounds__(kBlock)
+k_spmv_ell_col(int n, int width, const V* __restrict__ ev, const int* __restrict__ er, const X* __restrict__ x,
+               X* __restrict__ y) {
+    const int j = (int)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (j >= n) return;
+    const X xj = x[j];
+    size_t off = (size_t)j;
+    for (int k = 0; k < width; ++k, off += (size_t)n) {
+        const X v = (X)widen(ev[off]);
+        if (v != (X)0) atomic_add(&y[er[off]], v * xj);
+    }
+}
+
+// ------------------------------------------------------------- COO
+
+template <typename V, typename X>
+__global__ void __launch_bounds__(kBlock)
+k_spmv_coo_col(int64_t nnz, const int* __restrict__ jcol, const int* __restrict__ irow_t,
+               const V* __restrict__ val_t, const X* __restrict__ x, X* __restrict__ y) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nnz; q += stride)
+        atomic_add(&y[irow_t[q]], (X)widen(val_t[q]) * x[jcol[q]]);
+}
+
+// Eight consecutive elements through 16-byte loads (the caller guarantees
+// 16-byte alignment of p).
+template <typename T>
+__device__ __forceinline__ void load8(const T* __restrict__ p, T (&o)[8]) {
+    constexpr int nv = (int)sizeof(T) * 8 / 16;
+    const uint4* q = reinterpret_cast<const uint4*>(p);
+    uint4 t[nv];
+#pragma unroll
+    for (int k = 0; k < nv; ++k) t[k] = q[k];
+    __builtin_memcpy(&o[0], &t[0], sizeof(T) * 8);
+}
+
+template <typename V, typename X>
+__global__ void __launch_bounds__(kBlock)
+k_spmv_coo_row(int n, int64_t nnz, const int* __restrict__ irow, const int* __restrict__ icol,
+               const V* __restrict__ val, const X* __restrict__ x, X* __restrict__ y,
+               Carry<X>* __restrict__ carries) {
+    constexpr int E = kCooPerThread;
+    __shared__ int s_first[kBlock];
+    __shared__ int s_wrow[kBlock / kWave];
+    __shared__ X s_wval[kBlock / kWave];
+
+    const int64_t tile0 = (int64_t)blockIdx.x * kCooTile;
+    const int64_t base = tile0 + (int64_t)threadIdx.x * E;
+    int r[E];
+    X pr[E];
+    if (base + E <= nnz) {
+        int c[E];
+        V v[E];
+        load8(irow + base, r);
+        load8(icol + base, c);
+        load8(val + base, v);
+#pragma unroll
+        for (int e = 0; e < E; ++e) pr[e] = (X)widen(v[e]) * x[c[e]];
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int64_t p = base + e;
+            if (p < nnz) { r[e] = irow[p]; pr[e] = (X)widen(val[p]) * x[icol[p]]; }
+            else { r[e] = n; pr[e] = 0; }
+        }
+    }
+    s_first[threadIdx.x] = r[0];
+
+    // trailing run of this thread's entries
+    X tail = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        if (e > 0 && r[e] != r[e - 1]) tail = 0;
+        tail += pr[e];
+    }
+    // inclusive segmented scan of (row, tail) over the wave; rows are
+    // sorted, so equal rows at both ends of a range mean one run
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    int srow = r[E - 1];
+    X sval = tail;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int orow = __shfl_up(srow, off, kWave);
+        const X oval = __shfl_up(sval, off, kWave);
+        if (lane >= off && orow == srow) sval += oval;
+    }
+    if (lane == kWave - 1) { s_wrow[w] = srow; s_wval[w] = sval; }
+    __syncthreads();
+    int prow = -1;
+    X pval = 0;
+    for (int k = 0; k < w; ++k) {
+        const int wr = s_wrow[k];
+        const X wv = s_wval[k];
+        if (wr == prow) pval += wv; else { prow = wr; pval = wv; }
+    }
+    if (prow == srow) sval += pval;
+    // exclusive value = inclusive value of the previous thread
+    int crow = __shfl_up(srow, 1, kWave);
+    X cval = __shfl_up(sval, 1, kWave);
+    if (lane == 0) { crow = prow; cval = pval; }
+
+    X acc = (crow == r[0]) ? cval : (X)0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        if (e > 0 && r[e] != r[e - 1]) {
+            if (r[e - 1] < n) y[r[e - 1]] = acc;
+            acc = 0;
+        }
+        acc += pr[e];
+    }
+    int next;
+    if (threadIdx.x + 1 < kBlock) next = s_first[threadIdx.x + 1];
+    else next = (tile0 + kCooTile < nnz) ? irow[tile0 + kCooTile] : -2;
+    const bool cont = (next == r[E - 1]);
+    if (!cont && r[E - 1] < n) y[r[E - 1]] = acc;
+    if (threadIdx.x == kBlock - 1) {
+        Carry<X> cr;
+        cr.row = cont ? r[E - 1] : -1;
+        cr.pad = 0;
+        cr.val = cont ? acc : (X)0;
+        carries[blockIdx.x] = cr;
+    }
+}
+
+// Adds each row's carries from the workgroups it spans, in workgroup order.
+template <typename X>
+__global__ void __launch_bounds__(kBlock)
+k_coo_fixup(int nb, const Carry<X>* __restrict__ c, X* __restrict__ y) {
+    const int b = blockIdx.x * kBlock + threadIdx.x;
+    if (b >= nb) return;
+    const int r = c[b].row;
+    if (r < 0 || (b > 0 && c[b - 1].row == r)) return;
+    X s = c[b].val;
+    for (int k = b + 1; k < nb && c[k].row == r; ++k) s += c[k].val;
+    y[r] += s;
+}
+
+size_t coo_carry_bytes(int64_t nnz) {
+    const int64_t nb = (nnz + kCooTile - 1) / kCooTile;
+    return (size_t)(nb > 0 ? nb : 1) * sizeof(Carry<double>);
+}
+
+// ---------------------------------------------------------- dispatch
+
+__global__ void __launch_bounds__(kBlock) k_fill_zero(uint32_t* p, int64_t words) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < words; i += stride) p[i] = 0u;
+}
+
+hipError_t launch_fill_zero(void* y, int64_t bytes, hipStream_t s) {
+    const int64_t words = bytes / 4;
+    int64_t blocks = (words + kBlock - 1) / kBlock;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(kBlock), 0, s, (uint32_t*)y, words);
+    return hipGetLastError();
+}
+
+static inline unsigned grid_for(int64_t items, int per_block) {
+    return (unsigned)((items + per_block - 1) / per_block);
+}
+
+#define SPMV_DISPATCH(dtype, CALL)                                  \
+    switch (dtype) {                                                \
+        case 0: { typedef double V; typedef double X; CALL; break; } \
+        case 1: { typedef float V; typedef float X; CALL; break; }   \
+        case 2: { typedef bf16_t V; typedef float X; CALL; break; }  \
+        default: { typedef f16_t V; typedef float X; CALL; break; }  \
+    }
+
+hipError_t launch_spmv_crs_scalar(int dtype, int n, const int* irp, const int* icol, const void* val,
+                                  const void* x, void* y, hipStream_t s) {
+    SPMV_DISPATCH(dtype, hipLaunchKernelGGL((k_spmv_crs_scalar<V, X>), dim3(grid_for(n, kBlock)), dim3(kBlock),
+                                            0, s, n, irp, icol, (const V*)val, (const X*)x, (X*)y));
+    return hipGetLastError();
+}
+
+template <typename V, typename X>
+static void crs_vector_w(int width, int n, const int* irp, const int* icol, const void* val, const void* x,
+                         void* y, hipStream_t s) {
+#define CRSV(W) hipLaunchKernelGGL((k_spmv_crs_vector<V, X, W>), dim3(grid_for(n, kBlock / W)), dim3(kBlock), 0, s, \
+                                   n, irp, icol, (const V*)val, (const X*)x, (X*)y)
+    switch (width) {
+        case 2: CRSV(2); break;
+        case 4: CRSV(4); break;
+        case 8: CRSV(8); break;
+        case 16: CRSV(16); break;
+        case 32: CRSV(32); break;
+        default: CRSV(64); break;
+    }
+#undef CRSV
+}
+
+hipError_t launch_spmv_crs_vector(int dtype, int width, int n, const int* irp, const int* icol, const void* val,
+                                  const void* x, void* y, hipStream_t s) {
+    SPMV_DISPATCH(dtype, (crs_vector_w<V, X>(width, n, irp, icol, val, x, y, s)));
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_ell_row(int dtype, int n, int width, const void* ev, const int* ec, const void* x,
+                               void* y, hipStream_t s) {
+    SPMV_DISPATCH(dtype, hipLaunchKernelGGL((k_spmv_ell_row<V, X>), dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s,
+                                            n, width, (const V*)ev, ec, (const X*)x, (X*)y));
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_ell_col(int dtype, int n, int width, const void* ev, const int* er, const void* x,
+                               void* y, hipStream_t s) {
+    const int xb = dtype == 0 ? 8 : 4;
+    hipError_t e = launch_fill_zero(y, (int64_t)n * xb, s);
+    if (e != hipSuccess) return e;
+    SPMV_DISPATCH(dtype, hipLaunchKernelGGL((k_spmv_ell_col<V, X>), dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s,
+                                            n, width, (const V*)ev, er, (const X*)x, (X*)y));
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_coo_col(int dtype, int64_t nnz, const int* jcol, const int* irow_t, const void* val_t,
+                               const void* x, void* y, hipStream_t s) {
+    int64_t blocks = (nnz + kBlock - 1) / kBlock;
+    if (blocks > 16384) blocks = 16384;
+    if (blocks < 1) blocks = 1;
+    SPMV_DISPATCH(dtype, hipLaunchKernelGGL((k_spmv_coo_col<V, X>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                                            nnz, jcol, irow_t, (const V*)val_t, (const X*)x, (X*)y));
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_coo_row(int dtype, int n, int64_t nnz, const int* irow, const int* icol, const void* val,
+                               const void* x, void* y, void* carries, hipStream_t s) {
+    const int nb = (int)((nnz + kCooTile - 1) / kCooTile);
+    if (nb == 0) return hipSuccess;
+    SPMV_DISPATCH(dtype, {
+        hipLaunchKernelGGL((k_spmv_coo_row<V, X>), dim3(nb), dim3(kBlock), 0, s, n, nnz, irow, icol,
+                           (const V*)val, (const X*)x, (X*)y, (Carry<X>*)carries);
+        hipLaunchKernelGGL((k_coo_fixup<X>), dim3(grid_for(nb, kBlock)), dim3(kBlock), 0, s, nb,
+                           (const Carry<X>*)carries, (X*)y);
+    });
+    return hipGetLastError();
+}
+
+}  // namespace spmvat

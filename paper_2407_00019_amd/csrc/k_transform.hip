@@ -1,0 +1,485 @@
+// Run-time transformations of section 2.1 on gfx950.
+//
+//  * expand_ptr   COO-Row IROW from the row pointer, and COO-Column's column
+//                 index from the CCS column pointer (Phase II).
+//  * CRS -> CCS   Phase I: column counts (global atomics), exclusive scan
+//                 into column pointers, scatter of packed (position, row)
+//                 keys through per-column atomic cursors, then a per-column
+//                 sort of the keys by CRS position.  The sort turns the
+//                 scheduling-dependent scatter order into the paper's stable
+//                 order (by row, then by position within the row), so every
+//                 output array is deterministic and bit-exact.
+//  * ELL pack     slot-major VAL(n, width) / index arrays with zero padding.
+#include "common.h"
+#include "kernels.h"
+
+namespace spmvat {
+
+typedef unsigned long long u64;
+
+// ------------------------------------------------------------ helpers
+
+// Exclusive scan of one int per thread over a 256-thread workgroup.
+__device__ __forceinline__ int block_excl_scan(int v, int* sh, int& total) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    int x = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        int y = __shfl_up(x, off, kWave);
+        if (lane >= off) x += y;
+    }
+    if (lane == kWave - 1) sh[w] = x;
+    __syncthreads();
+    int pre = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kBlock / kWave; ++k) {
+        int t = sh[k];
+        pre += (k < w) ? t : 0;
+        tot += t;
+    }
+    __syncthreads();
+    total = tot;
+    return pre + x - v;
+}
+
+// Loads ptr[r0 .. r0+rows] of one 256-line tile into LDS.
+__device__ __forceinline__ void load_ptr_tile(const int* __restrict__ ptr, int r0, int rows, int* sp) {
+    for (int t = threadIdx.x; t <= rows; t += kBlock) sp[t] = ptr[r0 + t];
+    __syncthreads();
+}
+
+// -------------------------------------------------------- ptr expansion
+// Workgroup = 256 consecutive lines; its positions [ptr[r0], ptr[r0+256])
+// are walked with a stride of 256 (coalesced stores), each position's line
+// found by binary search in the LDS copy of the pointer slice.
+
+__global__ void __launch_bounds__(kBlock)
+k_expand_ptr(int n, const int* __restrict__ ptr, int* __restrict__ out) {
+    __shared__ int sp[kBlock + 1];
+    const int r0 = (int)xcd_block(blockIdx.x, gridDim.x) * kBlock;
+    const int rows = min(kBlock, n - r0);
+    load_ptr_tile(ptr, r0, rows, sp);
+    const int q1 = sp[rows];
+    for (int q = sp[0] + threadIdx.x; q < q1; q += kBlock)
+        out[q] = r0 + last_le(sp, 0, rows - 1, q);
+}
+
+hipError_t launch_expand_ptr(int n, const int* ptr, int* out, hipStream_t s) {
+    unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_expand_ptr, dim3(blocks), dim3(kBlock), 0, s, n, ptr, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------ Phase I: column counts
+
+__global__ void __launch_bounds__(kBlock)
+k_col_count(int64_t nnz, const int* __restrict__ icol, int* __restrict__ cnt) {
+    const int64_t nv = nnz >> 2;
+    const int4* ic4 = reinterpret_cast<const int4*>(icol);
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nv; q += stride) {
+        int4 c = ic4[q];
+        atomicAdd(&cnt[c.x], 1);
+        atomicAdd(&cnt[c.y], 1);
+        atomicAdd(&cnt[c.z], 1);
+        atomicAdd(&cnt[c.w], 1);
+    }
+    if (blockIdx.x == 0)
+        for (int64_t p = (nv << 2) + threadIdx.x; p < nnz; p += kBlock) atomicAdd(&cnt[icol[p]], 1);
+}
+
+hipError_t launch_col_count(int64_t nnz, const int* icol, int* cnt, hipStream_t s) {
+    int64_t blocks = ((nnz >> 2) + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_col_count, dim3((unsigned)blocks), dim3(kBlock), 0, s, nnz, icol, cnt);
+    return hipGetLastError();
+}
+
+// ------------------------------------- Phase I: exclusive scan of counts
+// Reduce-then-scan over tiles of 4096 counts: (A) tile sums, longest
+// column, and lists of the columns too long for the one-thread sort;
+// (B) one workgroup scans the tile sums; (C) each tile rescans with its
+// offset and writes ccp and the scatter cursors.
+
+constexpr int kScanPer = kScanTile / kBlock;   // 16 counts per thread
+
+__global__ void __launch_bounds__(kBlock)
+k_scan_reduce(int n, const int* __restrict__ cnt, int* __restrict__ bsum, int* __restrict__ mid_list,
+              int* __restrict__ long_list, ColSummary* __restrict__ sum) {
+    __shared__ int sh[kBlock / kWave];
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+    int s = 0, mx = 0;
+#pragma unroll
+    for (int e = 0; e < kScanPer; ++e) {
+        const int j = base + e;
+        if (j < n) {
+            const int c = cnt[j];
+            s += c;
+            mx = max(mx, c);
+            if (c > kSortSmall) {
+                if (c <= kSortMid) mid_list[atomicAdd(&sum->n_mid, 1)] = j;
+                else long_list[atomicAdd(&sum->n_long, 1)] = j;
+            }
+        }
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(&sum->max_len, mx);
+    int total;
+    block_excl_scan(s, sh, total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_scan_top(int nb, int n, int* __restrict__ bsum, int* __restrict__ ccp, ColSummary* __restrict__ sum) {
+    __shared__ int sh[kBlock / kWave];
+    int carry = 0;
+    for (int base = 0; base < nb; base += kBlock) {
+        const int j = base + threadIdx.x;
+        const int v = j < nb ? bsum[j] : 0;
+        int total;
+        const int ex = block_excl_scan(v, sh, total);
+        if (j < nb) bsum[j] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) {
+        sum->total = carry;
+        ccp[n] = carry;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_scan_apply(int n, const int* cnt, const int* __restrict__ bsum, int* __restrict__ ccp, int* cursor) {
+    // cnt and cursor are one array: every count is read before the same
+    // thread overwrites it with its cursor (no restrict on either)
+    __shared__ int sh[kBlock / kWave];
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+    int c[kScanPer];
+    int s = 0;
+#pragma unroll
+    for (int e = 0; e < kScanPer; ++e) {
+        c[e] = (base + e < n) ? cnt[base + e] : 0;
+        s += c[e];
+    }
+    int total;
+    int run = bsum[blockIdx.x] + block_excl_scan(s, sh, total);
+#pragma unroll
+    for (int e = 0; e < kScanPer; ++e) {
+        if (base + e < n) {
+            ccp[base + e] = run;
+            cursor[base + e] = run;
+        }
+        run += c[e];
+    }
+}
+
+size_t col_scan_bsum_count(int n) { return (size_t)((n + kScanTile - 1) / kScanTile); }
+
+hipError_t launch_col_scan(int n, const int* cnt, int* ccp, int* cursor, int* bsum, int* mid_list,
+                           int* long_list, ColSummary* sum, hipStream_t s) {
+    const int nb = (int)col_scan_bsum_count(n);
+    hipError_t e = hipMemsetAsync(sum, 0, sizeof(ColSummary), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, n, cnt, bsum, mid_list, long_list, sum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, nb, n, bsum, ccp, sum);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, s, n, cnt, bsum, ccp, cursor);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------- Phase I: the scatter
+// Each CRS entry (position q, row r, column c) claims a slot of column c
+// through its cursor and stores the key (q << 32 | r) there.  Slot order
+// inside a column depends on scheduling; the sort below fixes it.
+
+__global__ void __launch_bounds__(kBlock)
+k_ccs_scatter(int n, const int* __restrict__ irp, const int* __restrict__ icol, int* __restrict__ cursor,
+              u64* __restrict__ keys) {
+    __shared__ int sp[kBlock + 1];
+    const int r0 = (int)xcd_block(blockIdx.x, gridDim.x) * kBlock;
+    const int rows = min(kBlock, n - r0);
+    load_ptr_tile(irp, r0, rows, sp);
+    const int q1 = sp[rows];
+    for (int q = sp[0] + threadIdx.x; q < q1; q += kBlock) {
+        const int r = r0 + last_le(sp, 0, rows - 1, q);
+        const int slot = atomicAdd(&cursor[icol[q]], 1);
+        keys[slot] = ((u64)(uint32_t)q << 32) | (uint32_t)r;
+    }
+}
+
+hipError_t launch_ccs_scatter(int n, const int* irp, const int* icol, int* cursor, u64* keys,
+                              hipStream_t s) {
+    unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_ccs_scatter, dim3(blocks), dim3(kBlock), 0, s, n, irp, icol, cursor, keys);
+    return hipGetLastError();
+}
+
+// --------------------------------------- Phase I: per-column key sort
+// Keys are unique (one per CRS position), so sorting them by value gives
+// the one stable order.  Columns of up to kSortSmall entries: one thread,
+// insertion sort in place (the scatter leaves them nearly sorted).  Up to
+// kSortMid: one workgroup, bitonic sort in LDS.  Longer: chunks sorted in
+// LDS, then merge passes in global memory.  Every path ends by emitting
+// irow_t[q] = row and val_t[q] = val[position] for its column.
+
+template <typename R>
+__device__ __forceinline__ void emit(int q, u64 key, const R* __restrict__ val, int* __restrict__ irow_t,
+                                     R* __restrict__ val_t) {
+    irow_t[q] = (int)(uint32_t)key;
+    val_t[q] = val[key >> 32];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock)
+k_sort_small(int n, const int* __restrict__ ccp, u64* __restrict__ keys, const R* __restrict__ val,
+             int* __restrict__ irow_t, R* __restrict__ val_t) {
+    const int j = (int)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (j >= n) return;
+    const int s = ccp[j], e = ccp[j + 1];
+    if (e - s > kSortSmall || e == s) return;
+    u64 prev = keys[s];
+    for (int a = s + 1; a < e; ++a) {
+        const u64 k = keys[a];
+        if (k > prev) { prev = k; continue; }
+        keys[a] = prev;
+        int b = a - 2;
+        while (b >= s) {
+            const u64 t = keys[b];
+            if (t < k) break;
+            keys[b + 1] = t;
+            --b;
+        }
+        keys[b + 1] = k;
+    }
+    for (int q = s; q < e; ++q) emit<R>(q, keys[q], val, irow_t, val_t);
+}
+
+// Bitonic sort of up to kSortMid keys in LDS (pad with all-ones).
+__device__ void lds_bitonic(u64* sh, int len, int cap) {
+    int p = 1;
+    while (p < len) p <<= 1;
+    for (int i = len + threadIdx.x; i < p; i += kBlock) sh[i] = ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= p; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < p; i += kBlock) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const u64 a = sh[i], b = sh[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((a > b) == up) { sh[i] = b; sh[ixj] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    (void)cap;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock)
+k_sort_mid(const int* __restrict__ list, const int* __restrict__ ccp, u64* __restrict__ keys,
+           const R* __restrict__ val, int* __restrict__ irow_t, R* __restrict__ val_t) {
+    __shared__ u64 sh[kSortMid];
+    const int j = list[blockIdx.x];
+    const int s = ccp[j], len = ccp[j + 1] - s;
+    for (int i = threadIdx.x; i < len; i += kBlock) sh[i] = keys[s + i];
+    lds_bitonic(sh, len, kSortMid);
+    for (int i = threadIdx.x; i < len; i += kBlock) emit<R>(s + i, sh[i], val, irow_t, val_t);
+}
+
+// Long columns: sort chunks of kSortMid keys in place.
+__global__ void __launch_bounds__(kBlock)
+k_sort_chunks(int start, int len, u64* __restrict__ keys) {
+    __shared__ u64 sh[kSortMid];
+    const int c0 = blockIdx.x * kSortMid;
+    const int cl = min(kSortMid, len - c0);
+    u64* src = keys + start + c0;
+    for (int i = threadIdx.x; i < cl; i += kBlock) sh[i] = src[i];
+    lds_bitonic(sh, cl, kSortMid);
+    for (int i = threadIdx.x; i < cl; i += kBlock) src[i] = sh[i];
+}
+
+// Number of keys in [lo, hi) of a sorted run that are < key.
+__device__ __forceinline__ int count_less(const u64* a, int lo, int hi, u64 key) {
+    int l = lo, h = hi;
+    while (l < h) {
+        const int m = (l + h) >> 1;
+        if (a[m] < key) l = m + 1; else h = m;
+    }
+    return l - lo;
+}
+
+// One merge pass: sorted runs of width w pair up into runs of 2w.  Each key
+// lands at its index in its run plus its rank in the partner run.
+__global__ void __launch_bounds__(kBlock)
+k_merge_pass(int len, int w, const u64* __restrict__ src, u64* __restrict__ dst) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= len) return;
+    const u64 key = src[i];
+    const int g = (int)(((int64_t)i / (2 * (int64_t)w)) * 2 * w);
+    const int mid = (int)min((int64_t)g + w, (int64_t)len);
+    const int end = (int)min((int64_t)g + 2 * (int64_t)w, (int64_t)len);
+    int out;
+    if (i < mid) out = i + count_less(src, mid, end, key);
+    else out = g + (i - mid) + count_less(src, g, mid, key);
+    dst[out] = key;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock)
+k_emit_range(int start, int len, const u64* __restrict__ sorted, const R* __restrict__ val,
+             int* __restrict__ irow_t, R* __restrict__ val_t) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) emit<R>(start + i, sorted[i], val, irow_t, val_t);
+}
+
+// Columns longer than the merge scratch: each key's final index is its index
+// in its (sorted) chunk plus the number of smaller keys in every other chunk.
+template <typename R>
+__global__ void __launch_bounds__(kBlock)
+k_rank_emit(int start, int len, const u64* __restrict__ keys, const R* __restrict__ val, int* __restrict__ irow_t,
+            R* __restrict__ val_t) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= len) return;
+    const u64* a = keys + start;
+    const u64 key = a[i];
+    const int mine = i / kSortMid;
+    int rank = i - mine * kSortMid;
+    const int chunks = (len + kSortMid - 1) / kSortMid;
+    for (int c = 0; c < chunks; ++c) {
+        if (c == mine) continue;
+        rank += count_less(a, c * kSortMid, min(len, (c + 1) * kSortMid), key);
+    }
+    emit<R>(start + rank, key, val, irow_t, val_t);
+}
+
+template <typename R>
+static hipError_t rank_emit_t(int start, int len, const u64* keys, const void* val, int* irow_t, void* val_t,
+                              hipStream_t s) {
+    unsigned blocks = (unsigned)((len + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_rank_emit<R>, dim3(blocks), dim3(kBlock), 0, s, start, len, keys, (const R*)val, irow_t,
+                       (R*)val_t);
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t sort_small_t(int n, const int* ccp, u64* keys, const void* val, int* irow_t, void* val_t,
+                               hipStream_t s) {
+    unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_sort_small<R>, dim3(blocks), dim3(kBlock), 0, s, n, ccp, keys,
+                       (const R*)val, irow_t, (R*)val_t);
+    return hipGetLastError();
+}
+
+hipError_t launch_ccs_sort_small(int n, const int* ccp, u64* keys, const void* val, int vbytes,
+                                 int* irow_t, void* val_t, hipStream_t s) {
+    switch (vbytes) {
+        case 8: return sort_small_t<uint64_t>(n, ccp, keys, val, irow_t, val_t, s);
+        case 4: return sort_small_t<uint32_t>(n, ccp, keys, val, irow_t, val_t, s);
+        default: return sort_small_t<uint16_t>(n, ccp, keys, val, irow_t, val_t, s);
+    }
+}
+
+template <typename R>
+static hipError_t sort_mid_t(int count, const int* list, const int* ccp, u64* keys, const void* val,
+                             int* irow_t, void* val_t, hipStream_t s) {
+    hipLaunchKernelGGL(k_sort_mid<R>, dim3(count), dim3(kBlock), 0, s, list, ccp, keys, (const R*)val,
+                       irow_t, (R*)val_t);
+    return hipGetLastError();
+}
+
+hipError_t launch_ccs_sort_mid(int count, const int* list, const int* ccp, u64* keys, const void* val,
+                               int vbytes, int* irow_t, void* val_t, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    switch (vbytes) {
+        case 8: return sort_mid_t<uint64_t>(count, list, ccp, keys, val, irow_t, val_t, s);
+        case 4: return sort_mid_t<uint32_t>(count, list, ccp, keys, val, irow_t, val_t, s);
+        default: return sort_mid_t<uint16_t>(count, list, ccp, keys, val, irow_t, val_t, s);
+    }
+}
+
+template <typename R>
+static hipError_t emit_t(int start, int len, const u64* sorted, const void* val, int* irow_t,
+                         void* val_t, hipStream_t s) {
+    unsigned blocks = (unsigned)((len + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_emit_range<R>, dim3(blocks), dim3(kBlock), 0, s, start, len, sorted,
+                       (const R*)val, irow_t, (R*)val_t);
+    return hipGetLastError();
+}
+
+hipError_t launch_ccs_sort_long(int start, int len, u64* keys, u64* tmp, const void* val, int vbytes,
+                                int* irow_t, void* val_t, hipStream_t s) {
+    const unsigned chunks = (unsigned)((len + kSortMid - 1) / kSortMid);
+    hipLaunchKernelGGL(k_sort_chunks, dim3(chunks), dim3(kBlock), 0, s, start, len, keys);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (tmp == nullptr) {
+        switch (vbytes) {
+            case 8: return rank_emit_t<uint64_t>(start, len, keys, val, irow_t, val_t, s);
+            case 4: return rank_emit_t<uint32_t>(start, len, keys, val, irow_t, val_t, s);
+            default: return rank_emit_t<uint16_t>(start, len, keys, val, irow_t, val_t, s);
+        }
+    }
+    u64* src = keys + start;
+    u64* dst = tmp;
+    const unsigned blocks = (unsigned)((len + kBlock - 1) / kBlock);
+    for (int64_t w = kSortMid; w < len; w *= 2) {
+        hipLaunchKernelGGL(k_merge_pass, dim3(blocks), dim3(kBlock), 0, s, len, (int)w, src, dst);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        u64* t = src; src = dst; dst = t;
+    }
+    switch (vbytes) {
+        case 8: return emit_t<uint64_t>(start, len, src, val, irow_t, val_t, s);
+        case 4: return emit_t<uint32_t>(start, len, src, val, irow_t, val_t, s);
+        default: return emit_t<uint16_t>(start, len, src, val, irow_t, val_t, s);
+    }
+}
+
+// ------------------------------------------------------------- ELL pack
+// Thread per line, a chunk of 64 slots per grid row.  Stores of slot k for
+// 64 consecutive lines are contiguous (slot-major layout); a line's stored
+// entries are read in order.  Padding: value bits 0 (+0.0), index = line.
+
+constexpr int kEllSlotChunk = 64;
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock)
+k_ell_pack(int n, int width, const int* __restrict__ ptr, const int* __restrict__ idx, const R* __restrict__ val,
+           R* __restrict__ ev, int* __restrict__ ei) {
+    const int i = (int)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int a = ptr[i], len = ptr[i + 1] - a;
+    const int k0 = blockIdx.y * kEllSlotChunk;
+    const int k1 = min(width, k0 + kEllSlotChunk);
+    size_t off = (size_t)k0 * (size_t)n + (size_t)i;
+    for (int k = k0; k < k1; ++k, off += (size_t)n) {
+        if (k < len) {
+            ev[off] = val[a + k];
+            ei[off] = idx[a + k];
+        } else {
+            ev[off] = (R)0;
+            ei[off] = i;
+        }
+    }
+}
+
+template <typename R>
+static hipError_t ell_pack_t(int n, int width, const int* ptr, const int* idx, const void* val, void* ev,
+                             int* ei, hipStream_t s) {
+    dim3 grid((unsigned)((n + kBlock - 1) / kBlock), (unsigned)((width + kEllSlotChunk - 1) / kEllSlotChunk));
+    hipLaunchKernelGGL(k_ell_pack<R>, grid, dim3(kBlock), 0, s, n, width, ptr, idx, (const R*)val, (R*)ev, ei);
+    return hipGetLastError();
+}
+
+hipError_t launch_ell_pack(int n, int width, const int* ptr, const int* idx, const void* val, int vbytes,
+                           void* ell_val, int* ell_idx, hipStream_t s) {
+    if (width == 0) return hipSuccess;
+    switch (vbytes) {
+        case 8: return ell_pack_t<uint64_t>(n, width, ptr, idx, val, ell_val, ell_idx, s);
+        case 4: return ell_pack_t<uint32_t>(n, width, ptr, idx, val, ell_val, ell_idx, s);
+        default: return ell_pack_t<uint16_t>(n, width, ptr, idx, val, ell_val, ell_idx, s);
+    }
+}
+
+}  // namespace spmvat

@@ -1,0 +1,79 @@
+// Host-side launchers of the spmvat kernels (internal to libspmvat.so).
+// Each enqueues on `s` and returns the launch's hipError_t.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace spmvat {
+
+// Output of the row-statistics kernel (one per plan, in plan workspace).
+struct RowStats {
+    unsigned long long s1, s2;   // sum l_i, sum l_i^2
+    int32_t max_len;
+    uint32_t min_len;            // starts at 0xffffffff
+    uint32_t flags;              // 1 irp[0]!=0, 2 irp[n]!=nnz, 4 decreasing irp, 8 column out of range
+    int32_t pad;
+};
+
+// Column-count summary written by the CCS scan (read back by the host).
+struct ColSummary {
+    int32_t total;        // sum of counts (= nnz)
+    int32_t max_len;      // longest column
+    int32_t n_mid;        // columns with kSortSmall < len <= kSortMid
+    int32_t n_long;       // columns with len > kSortMid
+};
+
+constexpr int kSortSmall = 256;   // sorted by one thread in place
+constexpr int kSortMid = 8192;    // sorted by one workgroup in LDS
+constexpr int kScanTile = 4096;   // counts per workgroup in the column scan
+
+// Carry of the COO-Row segmented reduction: one per workgroup tile.
+template <typename X> struct Carry { int32_t row; int32_t pad; X val; };
+constexpr int kCooPerThread = 8;
+constexpr int kCooTile = 256 * kCooPerThread;
+
+// ---- statistics
+hipError_t launch_row_stats(int n, int64_t nnz, const int* irp, const int* icol, RowStats* out,
+                            hipStream_t s);
+
+// ---- transformations
+hipError_t launch_expand_ptr(int n, const int* ptr, int* out, hipStream_t s);
+hipError_t launch_col_count(int64_t nnz, const int* icol, int* cnt, hipStream_t s);
+hipError_t launch_col_scan(int n, const int* cnt, int* ccp, int* cursor, int* bsum,
+                           int* mid_list, int* long_list, ColSummary* sum, hipStream_t s);
+size_t col_scan_bsum_count(int n);
+hipError_t launch_ccs_scatter(int n, const int* irp, const int* icol, int* cursor,
+                              unsigned long long* keys, hipStream_t s);
+hipError_t launch_ccs_sort_small(int n, const int* ccp, unsigned long long* keys, const void* val,
+                                 int vbytes, int* irow_t, void* val_t, hipStream_t s);
+hipError_t launch_ccs_sort_mid(int count, const int* list, const int* ccp, unsigned long long* keys,
+                               const void* val, int vbytes, int* irow_t, void* val_t, hipStream_t s);
+// Sorts one long column [start, start+len) of keys, using tmp (len keys) as
+// ping-pong space, and writes irow_t / val_t for it.  tmp = nullptr: rank
+// across sorted chunks instead (no scratch, slower).
+hipError_t launch_ccs_sort_long(int start, int len, unsigned long long* keys, unsigned long long* tmp,
+                                const void* val, int vbytes, int* irow_t, void* val_t, hipStream_t s);
+hipError_t launch_ell_pack(int n, int width, const int* ptr, const int* idx, const void* val,
+                           int vbytes, void* ell_val, int* ell_idx, hipStream_t s);
+
+// ---- SpMV (dtype: 0 F64, 1 F32, 2 BF16, 3 F16)
+hipError_t launch_fill_zero(void* y, int64_t bytes, hipStream_t s);
+hipError_t launch_spmv_crs_scalar(int dtype, int n, const int* irp, const int* icol, const void* val,
+                                  const void* x, void* y, hipStream_t s);
+hipError_t launch_spmv_crs_vector(int dtype, int width, int n, const int* irp, const int* icol,
+                                  const void* val, const void* x, void* y, hipStream_t s);
+hipError_t launch_spmv_ell_row(int dtype, int n, int width, const void* ev, const int* ec,
+                               const void* x, void* y, hipStream_t s);
+hipError_t launch_spmv_ell_col(int dtype, int n, int width, const void* ev, const int* er,
+                               const void* x, void* y, hipStream_t s);
+hipError_t launch_spmv_coo_row(int dtype, int n, int64_t nnz, const int* irow, const int* icol,
+                               const void* val, const void* x, void* y, void* carries, hipStream_t s);
+hipError_t launch_spmv_coo_col(int dtype, int64_t nnz, const int* jcol, const int* irow_t,
+                               const void* val_t, const void* x, void* y, hipStream_t s);
+size_t coo_carry_bytes(int64_t nnz);
+
+// ---- value conversion (to: 1 F32, 2 BF16, 3 F16)
+hipError_t launch_convert(int to, int64_t m, const double* in, void* out, hipStream_t s);
+
+}  // namespace spmvat

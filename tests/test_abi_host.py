@@ -1,0 +1,149 @@
+"""CPU checks of the C-ABI library: it loads, exports every entry point that
+include/spmvat.h declares, and its host-only logic (status strings, the
+off-line D* rule, the on-line format choice) agrees with the oracle.  No
+device work is done here."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    import paper_2407_00019_amd as spmvat
+    if not os.path.exists(spmvat.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return spmvat
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "spmvat.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported():
+    spmvat = _lib()
+    names = declared_functions()
+    assert len(names) >= 16
+    L = spmvat.lib()
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    spmvat = _lib()
+    assert spmvat.status_string(0) == "ok"
+    assert "limit" in spmvat.status_string(spmvat.SPMV_E_TOO_LARGE)
+    assert spmvat.status_string(99) == "unknown status"
+
+
+def test_workspace_size_grows_with_nnz():
+    spmvat = _lib()
+    a = spmvat.spmv_plan_workspace_bytes(10, 100)
+    b = spmvat.spmv_plan_workspace_bytes(10, 10_000_000)
+    assert a > 0 and b > a and b % 256 == 0
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_dstar_matches_oracle(seed):
+    spmvat = _lib()
+    rng = np.random.default_rng(seed)
+    m = int(rng.integers(0, 12))
+    d = np.round(rng.uniform(0, 4, m), 2).tolist()
+    if m > 2:
+        d[1] = d[0]          # ties
+    r = rng.uniform(0, 3, m).tolist()
+    feas = (rng.random(m) > 0.2).astype(int).tolist()
+    t = spmvat.at_table_build(d, r, feas, 1.0)
+    want = oracle.d_star(list(zip(d, r, [bool(f) for f in feas])), 1.0)
+    assert t.d_star == want
+    assert t.c == 1.0
+
+
+def _stats(n, nnz, max_row, d_mat):
+    spmvat = _lib()
+    st = spmvat.spmv_stats()
+    st.n, st.nnz, st.max_row, st.min_row, st.max_col = n, nnz, max_row, 1, -1
+    st.sum_len = nnz
+    st.mu = nnz / n
+    st.d_mat = d_mat
+    return st
+
+
+def test_paper_rule_and_memory_guard():
+    spmvat = _lib()
+    t = spmvat.at_table_build([0.1, 0.5, 1.0], [2.0, 0.8, 0.1], None, 1.0)
+    assert t.d_star == 0.5
+    st = _stats(1000, 27000, 27, 0.07)
+    f, v, why = spmvat.at_choose_format_stats(st, spmvat.F64, 1 << 40, t, 0)
+    assert (f, v, why.rule, why.feasible_ell) == (spmvat.ELL_ROW, 0, 0, 1)
+    st.d_mat = 0.5
+    assert spmvat.at_choose_format_stats(st, spmvat.F64, 1 << 40, t, 0)[0] == spmvat.CRS
+    st.d_mat = 0.07
+    # ELL-Row needs 27 * 1000 * 12 bytes: refuse below that
+    f, v, why = spmvat.at_choose_format_stats(st, spmvat.F64, 27 * 1000 * 12 - 1, t, 0)
+    assert f == spmvat.CRS and why.feasible_ell == 0
+    assert spmvat.at_choose_format_stats(st, spmvat.F64, 27 * 1000 * 12, t, 0)[0] == spmvat.ELL_ROW
+
+
+def _calibrated(spmvat, crs0, crs1, coo, ell, tr_coo, tr_ell, launch=0.0):
+    t = spmvat.at_table_build([], [], None, 1.0)
+    t.calibrated = 1
+    for b in range(spmvat.AT_DBUCKETS):
+        t.spmv_bps[spmvat.CRS][0][b] = crs0
+        t.spmv_bps[spmvat.CRS][1][b] = crs1
+        t.spmv_bps[spmvat.COO_ROW][0][b] = coo
+        t.spmv_bps[spmvat.ELL_ROW][0][b] = ell
+        t.trans_bps[spmvat.COO_ROW][b] = tr_coo
+        t.trans_bps[spmvat.ELL_ROW][b] = tr_ell
+    t.launch_s = launch
+    return t
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 8, 20, 100, 500])
+@pytest.mark.parametrize("dtype", [0, 1, 2])
+def test_k_aware_choice_matches_oracle(k, dtype):
+    """The library's amortised choice equals the oracle's argmin of
+    t_trans + k t_spmv over the same estimates (bytes / rate + launches)."""
+    spmvat = _lib()
+    n, nnz, w = 100000, 2_600_000, 27
+    st = _stats(n, nnz, w, 0.07)
+    vb = {0: 8, 1: 4, 2: 2}[dtype]
+    xb = 8 if dtype == 0 else 4
+    t = _calibrated(spmvat, 2.0e12, 3.0e12, 2.5e12, 4.0e12, 3.0e12, 2.0e12, 2e-6)
+    crs_b = (vb + 4) * nnz + 4 * (n + 1) + 2 * xb * n
+    coo_b = (vb + 8) * nnz + 2 * xb * n
+    ell_b = (vb + 4) * n * w + 2 * xb * n
+    tcrs = min(crs_b / 2.0e12, crs_b / 3.0e12) + 2e-6
+    cands = {
+        "coo_row": ((4 * (n + 1) + 4 * nnz) / 3.0e12 + 2e-6, coo_b / 2.5e12 + 4e-6),
+        "ell_row": (((vb + 4) * nnz + 4 * (n + 1) + ell_b - 2 * xb * n) / 2.0e12 + 2e-6, ell_b / 4.0e12 + 2e-6),
+    }
+    want = oracle.choose_k_aware(k, tcrs, cands)
+    f, v, why = spmvat.at_choose_format_stats(st, dtype, 1 << 40, t, k)
+    got = {spmvat.CRS: "crs", spmvat.COO_ROW: "coo_row", spmvat.ELL_ROW: "ell_row"}[f]
+    assert got == want
+    assert why.rule == 1
+    if got == "crs":
+        assert v == 1        # the faster CRS variant
+    else:
+        ts = cands[got][1]
+        assert why.k_break_even == pytest.approx((cands[got][0] / tcrs) / (1 - ts / tcrs))
+
+
+def test_uncalibrated_table_falls_back_to_paper_rule():
+    spmvat = _lib()
+    t = spmvat.at_table_build([0.3], [0.5], None, 1.0)
+    st = _stats(1000, 5000, 5, 0.2)
+    f, v, why = spmvat.at_choose_format_stats(st, 0, 1 << 40, t, 50)
+    assert why.rule == 0 and f == spmvat.ELL_ROW
+    t2 = spmvat.at_table_build([], [], None, 1.0)
+    assert math.isinf(t2.d_star)

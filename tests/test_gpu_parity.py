@@ -1,0 +1,283 @@
+"""GPU parity: the HIP path, called through the C ABI, against the CPU oracle
+on the same seeded inputs.
+
+Bar: index, pointer and transformed value arrays bit-exact; D_mat and its
+integer moments bit-exact; binary64 SpMV within relative L2 1e-13 in every
+format and variant, and bitwise equal when the data are small integers (all
+partial sums exact, so even the atomic formats must agree)."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from _gpu import F64, bits, host, lib_ready, oracle_transforms, stored_bits, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-13
+
+SMALL = [
+    # name, builder
+    ("laplace64", lambda: gen.laplace_64x64()),
+    ("stencil27_e9", lambda: gen.stencil27(9, 9, 9, 5)),
+    ("rand_sorted", lambda: gen.random_small(3001, 1, 12, True, False, 0.1, integer_values=False)),
+    ("rand_unsorted", lambda: gen.random_small(2500, 2, 9, False, False, 0.2, integer_values=False)),
+    ("rand_dups", lambda: gen.random_small(1700, 3, 9, False, True, 0.3, integer_values=False)),
+    ("mostly_empty", lambda: gen.random_small(5000, 4, 3, True, False, 0.9, integer_values=False)),
+    ("single_row", lambda: gen.random_small(1, 5, 1, True, False, 0.0, integer_values=False)),
+    ("no_entries", lambda: gen.random_small(300, 6, 0, True, False, 0.0, integer_values=False)),
+    ("powerlaw_small", lambda: gen.lognormal_matrix(40000, 16.0, 1.2, 7, 1, 4000)),
+    ("banded", lambda: gen.banded(7777, 40, 8)),
+]
+
+
+def arrow(n, seed, dense_cols=(0,), mid_col=None, mid_len=1000):
+    """Every row holds the dense columns; one more column holds mid_len
+    entries; plus a short random part.  Exercises the workgroup and
+    multi-pass column sorts."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for i in range(n):
+        c = set(dense_cols)
+        if mid_col is not None and i % max(1, n // mid_len) == 0:
+            c.add(mid_col)
+        c.update(rng.integers(0, n, size=int(rng.integers(0, 4))).tolist())
+        rows.append(sorted(c))
+    lens = np.array([len(r) for r in rows])
+    irp = np.zeros(n + 1, np.int64)
+    irp[1:] = np.cumsum(lens)
+    icol = np.concatenate([np.array(r, np.int32) for r in rows])
+    val = rng.standard_normal(icol.shape[0])
+    return gen.Crs(n, irp.astype(np.int32), icol, val, f"arrow_{n}")
+
+
+SMALL += [
+    ("arrow_mid", lambda: arrow(3000, 9, dense_cols=(5,), mid_col=77, mid_len=700)),
+    ("arrow_long", lambda: arrow(50000, 10, dense_cols=(0, 49999), mid_col=123, mid_len=5000)),
+]
+
+
+def run_gpu_all(m, x64):
+    import torch
+    spmvat = lib_ready()
+    irp, icol, val = to_dev(m)
+    xd = torch.from_numpy(x64).to("cuda:0")
+    plan = spmvat.Plan(irp, icol, val)
+    plan.set_limit(1 << 40)          # the memory guard has its own test
+    out = {"stats": plan.stats}
+    (out["irow"],) = plan.to_coo()
+    out["ccp"], out["irow_t"], out["val_t"] = plan.to_ccs()
+    (out["jcol"],) = plan.to_coo(column_wise=True)
+    (out["ell_val"], out["ell_col"]), out["ell_w"] = plan.to_ell()
+    (out["ellc_val"], out["ellc_row"]), out["ellc_w"] = plan.to_ell(column_wise=True)
+    out["max_col"] = plan.stats.max_col
+    ys = {}
+    for fmt, var in [(spmvat.CRS, 0), (spmvat.CRS, 1), (spmvat.CRS, 2), (spmvat.CRS, 4), (spmvat.CRS, 7),
+                     (spmvat.COO_ROW, 0), (spmvat.ELL_ROW, 0), (spmvat.COO_COL, 0), (spmvat.ELL_COL, 0)]:
+        ys[(fmt, var)] = host(plan.spmv(fmt, xd, variant=var))
+    out["y"] = ys
+    out = {k: (host(v) if hasattr(v, "cpu") else v) for k, v in out.items()}
+    plan.close()
+    return out
+
+
+def check_transforms(m, g, o):
+    assert np.array_equal(g["irow"], o["irow"])
+    assert np.array_equal(g["ccp"], o["ccp"])
+    assert np.array_equal(g["irow_t"], o["irow_t"])
+    assert np.array_equal(bits(g["val_t"]), bits(o["val_t"]))
+    assert np.array_equal(g["jcol"], o["jcol"])
+    assert g["ell_w"] == o["ell_w"]
+    assert np.array_equal(bits(g["ell_val"]), bits(o["ell_val"]))
+    assert np.array_equal(g["ell_col"], o["ell_col"])
+    assert g["ellc_w"] == o["ellc_w"] == g["max_col"]
+    assert np.array_equal(bits(g["ellc_val"]), bits(o["ellc_val"]))
+    assert np.array_equal(g["ellc_row"], o["ellc_row"])
+
+
+def check_stats(m, st):
+    s1, s2, mx, mn = oracle.row_moments(m.n, m.irp)
+    mu, sg, d = oracle.dmat_from_moments(m.n, s1, s2)
+    assert (st.sum_len, st.sum_len2, st.max_row, st.min_row) == (s1, s2, mx, mn)
+    assert bits(np.array([st.mu, st.sigma, st.d_mat])).tolist() == bits(np.array([mu, sg, d])).tolist()
+
+
+@pytest.mark.parametrize("name,builder", SMALL, ids=[s[0] for s in SMALL])
+def test_small_matrices_full_path(name, builder):
+    m = builder()
+    x = gen.x_uniform(m.n, 99)
+    g = run_gpu_all(m, x)
+    check_stats(m, g["stats"])
+    check_transforms(m, g, oracle_transforms(m))
+    yref = oracle.spmv_crs(m.n, m.irp, m.icol, m.val, x)
+    for key, y in g["y"].items():
+        assert oracle.rel_l2(y, yref) <= TOL64, (name, key, oracle.rel_l2(y, yref))
+
+
+@pytest.mark.parametrize("name,builder", SMALL[:6], ids=[s[0] for s in SMALL[:6]])
+def test_integer_data_is_bitwise_exact(name, builder):
+    m = builder()
+    rng = np.random.default_rng(3)
+    m.val = rng.integers(-5, 6, size=m.nnz).astype(np.float64)
+    x = rng.integers(-3, 4, size=m.n).astype(np.float64)
+    g = run_gpu_all(m, x)
+    yref = oracle.spmv_crs(m.n, m.irp, m.icol, m.val, x)
+    for key, y in g["y"].items():
+        assert np.array_equal(y, yref), (name, key)
+
+
+def test_laplace_x_one_exact():
+    m = gen.laplace_64x64()
+    g = run_gpu_all(m, np.ones(m.n))
+    i = np.arange(m.n)
+    want = ((i % 64 == 0) | (i % 64 == 63)).astype(float) + ((i // 64 == 0) | (i // 64 == 63)).astype(float)
+    for key, y in g["y"].items():
+        assert np.array_equal(y, want), key
+
+
+def test_transforms_and_coo_row_are_deterministic():
+    import torch
+    spmvat = lib_ready()
+    m = gen.lognormal_matrix(200000, 16.0, 1.2, 21, 1, 3000)
+    irp, icol, val = to_dev(m)
+    x = torch.from_numpy(gen.x_uniform(m.n, 4)).to("cuda:0")
+    res = []
+    for _ in range(2):
+        plan = spmvat.Plan(irp, icol, val)
+        ccp, irow_t, val_t = plan.to_ccs()
+        (jcol,) = plan.to_coo(column_wise=True)
+        plan.to_coo()
+        y = plan.spmv(spmvat.COO_ROW, x)
+        res.append([host(ccp), host(irow_t), bits(host(val_t)), host(jcol), bits(host(y))])
+        plan.close()
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.slow
+def test_stencil27_128_full_size():
+    """The headline workload at full size (n = 2,097,152, nnz = 55,742,968),
+    the same calls the benchmark times: every array bit-exact, every SpMV
+    within 1e-13."""
+    m = gen.stencil27_128()
+    assert m.nnz == 382 ** 3
+    x = gen.x_uniform(m.n, gen.seed_for(2))
+    g = run_gpu_all(m, x)
+    check_stats(m, g["stats"])
+    assert g["ell_w"] == 27 and g["max_col"] == 27
+    check_transforms(m, g, oracle_transforms(m))
+    yref = oracle.spmv_crs(m.n, m.irp, m.icol, m.val, x)
+    for key, y in g["y"].items():
+        assert oracle.rel_l2(y, yref) <= TOL64, (key, oracle.rel_l2(y, yref))
+
+
+@pytest.mark.slow
+def test_powerlaw_full_size():
+    """n = 4,194,304 lognormal rows (D_mat ~ 1.80): ELL-Row is refused by the
+    memory guard; everything else is checked against the oracle."""
+    import torch
+    spmvat = lib_ready()
+    m = gen.powerlaw()
+    x = gen.x_uniform(m.n, gen.seed_for(3))
+    irp, icol, val = to_dev(m)
+    xd = torch.from_numpy(x).to("cuda:0")
+    plan = spmvat.Plan(irp, icol, val)
+    check_stats(m, plan.stats)
+    s, sz = plan.sizes(spmvat.ELL_ROW)
+    assert s == spmvat.SPMV_E_TOO_LARGE
+    assert sz.width == oracle.max_len(m.n, m.irp)
+    with pytest.raises(spmvat.SpmvError) as ei:
+        plan.to_ell()
+    assert ei.value.status == spmvat.SPMV_E_TOO_LARGE
+    (irow,) = plan.to_coo()
+    ccp, irow_t, val_t = plan.to_ccs()
+    (jcol,) = plan.to_coo(column_wise=True)
+    (cv, cr), wc = plan.to_ell(column_wise=True)
+    o_irow = oracle.csr_to_coo_row(m.n, m.irp)
+    o_ccp, o_irow_t, o_val_t = oracle.csr_to_ccs(m.n, m.irp, m.icol, m.val)
+    assert np.array_equal(host(irow), o_irow)
+    assert np.array_equal(host(ccp), o_ccp)
+    assert np.array_equal(host(irow_t), o_irow_t)
+    assert np.array_equal(bits(host(val_t)), bits(o_val_t))
+    assert np.array_equal(host(jcol), oracle.ccs_to_coo_col(m.n, o_ccp))
+    o_cv, o_cr = oracle.to_ell(m.n, o_ccp, o_irow_t, o_val_t)
+    assert wc == oracle.max_len(m.n, o_ccp)
+    assert np.array_equal(bits(host(cv)), bits(o_cv))
+    assert np.array_equal(host(cr), o_cr)
+    yref = oracle.spmv_crs(m.n, m.irp, m.icol, m.val, x)
+    for fmt, var in [(spmvat.CRS, 0), (spmvat.CRS, 1), (spmvat.COO_ROW, 0), (spmvat.COO_COL, 0),
+                     (spmvat.ELL_COL, 0)]:
+        y = host(plan.spmv(fmt, xd, variant=var))
+        assert oracle.rel_l2(y, yref) <= TOL64, (fmt, var)
+    plan.close()
+
+
+def test_error_paths_leave_the_plan_usable():
+    import torch
+    spmvat = lib_ready()
+    m = gen.laplace_64x64()
+    irp, icol, val = to_dev(m)
+    dev = irp.device
+    ws = torch.empty(spmvat.spmv_plan_workspace_bytes(m.n, m.nnz), dtype=torch.uint8, device=dev)
+    # malformed CRS
+    bad_col = icol.clone()
+    bad_col[17] = m.n
+    for args in [(irp, bad_col, val), (irp + 1, icol, val)]:
+        with pytest.raises(spmvat.SpmvError) as ei:
+            spmvat.spmv_plan_create(m.n, m.nnz, *args, spmvat.F64, ws)
+        assert ei.value.status == spmvat.SPMV_E_MATRIX
+    dec = irp.clone()
+    dec[10], dec[11] = dec[11].item(), dec[10].item()
+    with pytest.raises(spmvat.SpmvError) as ei:
+        spmvat.spmv_plan_create(m.n, m.nnz, dec, icol, val, spmvat.F64, ws)
+    assert ei.value.status == spmvat.SPMV_E_MATRIX
+    # misaligned pointer
+    with pytest.raises(spmvat.SpmvError) as ei:
+        spmvat.spmv_plan_create(m.n, m.nnz - 1, irp, icol[1:], val[1:], spmvat.F64, ws)
+    assert ei.value.status == spmvat.SPMV_E_ARG
+    plan = spmvat.Plan(irp, icol, val)
+    x = torch.from_numpy(gen.x_uniform(m.n, 1)).to(dev)
+    for fmt in (spmvat.COO_ROW, spmvat.ELL_ROW, spmvat.COO_COL, spmvat.ELL_COL):
+        with pytest.raises(spmvat.SpmvError) as ei:
+            plan.spmv(fmt, x)
+        assert ei.value.status == spmvat.SPMV_E_NOT_READY
+    with pytest.raises(spmvat.SpmvError) as ei:
+        plan.to_coo(column_wise=True)
+    assert ei.value.status == spmvat.SPMV_E_NOT_READY
+    plan.to_ell()
+    plan.set_limit(1000)
+    with pytest.raises(spmvat.SpmvError) as ei:
+        plan.to_ccs()
+    assert ei.value.status == spmvat.SPMV_E_TOO_LARGE
+    # the ELL-Row built before the refusal still works
+    yref = oracle.spmv_crs(m.n, m.irp, m.icol, m.val, host(x))
+    assert oracle.rel_l2(host(plan.spmv(spmvat.ELL_ROW, x)), yref) <= TOL64
+    # short output buffer
+    plan.set_limit(1 << 40)
+    s, sz = plan.sizes(spmvat.COO_ROW)
+    short = torch.empty(sz.bytes[0] // 4 - 1, dtype=torch.int32, device=dev)
+    with pytest.raises(spmvat.SpmvError) as ei:
+        spmvat.csr_to_coo(plan.handle, 0, [short])
+    assert ei.value.status == spmvat.SPMV_E_ARG
+    plan.close()
+
+
+def test_convert_values_bits_match_oracle():
+    import torch
+    spmvat = lib_ready()
+    rng = np.random.default_rng(12)
+    v = np.concatenate([
+        rng.standard_normal(100000),
+        rng.standard_normal(20000) * np.exp2(rng.integers(-160, 130, 20000).astype(np.float64)),
+        np.array([0.0, -0.0, 65504.0, 65519.99, 65520.0, 1e6, -1e6, 5.96e-8, 2.98e-8, 1e-300, 3.4e38, 3.5e38]),
+    ])
+    # exact ties between neighbouring bfloat16 / binary16 values and one step either side
+    for step_exp in (-7, -10):
+        base = 1.0 + np.arange(1, 200) * 2.0 ** step_exp
+        mid = base + 2.0 ** (step_exp - 1)
+        v = np.concatenate([v, mid, np.nextafter(mid, 2), np.nextafter(mid, 0)])
+    vd = torch.from_numpy(v).to("cuda:0")
+    for dt in (spmvat.F32, spmvat.BF16, spmvat.F16):
+        got = stored_bits(spmvat.convert_values(vd, dt))
+        want = oracle.round_values(dt, v)
+        assert np.array_equal(got, want), dt
