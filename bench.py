@@ -1,0 +1,412 @@
+"""Benchmark of the run-time CRS transformation + SpMV hot path on one MI355X.
+
+One step is one pass of the whole path over the 27-point stencil on a 128^3
+grid (n = 2,097,152, nnz = 55,742,968, binary64): row statistics and D_mat
+(plan creation), the format decision, CRS -> COO-Row, CRS -> CCS,
+CCS -> COO-Column, CRS -> ELL-Row, CCS -> ELL-Column, SpMV in every format
+and CRS variant, and the reduced-precision rows (values rounded to binary32
+and bfloat16, SpMV with binary32 accumulation).  Inputs are resident in HBM
+before the timed region; output buffers are allocated once.
+
+Prints ONE JSON line.  `value` is the algorithmic HBM GB/s of the fastest
+binary64 SpMV format (bytes the method must move / mean kernel time),
+the headline of the metric "SpMV HBM GB/s (% peak) per format"; the
+per-format figures, transform cost in CRS-SpMV units (Eq. (2) read as
+t_trans / t_crs), SP (Eq. (1)) and R_ell (Eq. (3)) are reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "SpMV HBM GB/s (% peak) per format; transform time / CRS SpMV; jobs/s, p50/p99"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------ algorithmic bytes
+# What the method itself must move: each array read or written once, x and
+# y once each, ELL padding included (the method computes it).
+
+def spmv_bytes(fmt, n, nnz, width, vb, xb):
+    if fmt == "crs":
+        return (vb + 4) * nnz + 4 * (n + 1) + 2 * xb * n
+    if fmt in ("coo_row", "coo_col"):
+        return (vb + 8) * nnz + 2 * xb * n
+    if fmt in ("ell_row", "ell_col"):
+        return (vb + 4) * n * width + 2 * xb * n
+    raise ValueError(fmt)
+
+
+def transform_bytes(kind, n, nnz, width, vb):
+    if kind == "stats":
+        return 4 * (n + 1) + 4 * nnz
+    if kind in ("coo_row", "coo_col"):
+        return 4 * (n + 1) + 4 * nnz
+    if kind == "ccs":
+        return (2 * vb + 12) * nnz + 20 * n
+    if kind in ("ell_row", "ell_col"):
+        return (vb + 4) * nnz + 4 * (n + 1) + (vb + 4) * n * width
+    if kind == "convert":
+        return 8 * nnz + vb * nnz
+    raise ValueError(kind)
+
+
+# ------------------------------------------------------------- the GPU path
+
+class Timer:
+    """HIP events on torch's current stream, the stream every library call
+    here is launched on."""
+
+    def __init__(self):
+        import torch
+        self.torch = torch
+        self.marks = {}
+
+    def __call__(self, name, fn, *a, **k):
+        t = self.torch
+        e0, e1 = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+        e0.record()
+        r = fn(*a, **k)
+        e1.record()
+        self.marks.setdefault(name, []).append((e0, e1))
+        return r
+
+    def results_ms(self):
+        self.torch.cuda.synchronize()
+        return {k: [a.elapsed_time(b) for a, b in v] for k, v in self.marks.items()}
+
+    def clear(self):
+        self.marks = {}
+
+
+def alloc_like(spmvat, plan, fmt, vt, dev):
+    import torch
+    s, sz = spmvat.spmv_buffer_sizes(plan, fmt)
+    if s != spmvat.SPMV_OK:
+        return None, None, sz, s
+    vb = torch.empty(0, dtype=vt).element_size()
+    if fmt in (spmvat.COO_ROW, spmvat.COO_COL):
+        out = [torch.empty(sz.bytes[0] // 4, dtype=torch.int32, device=dev)]
+    elif fmt == spmvat.CCS:
+        out = [torch.empty(sz.bytes[0] // 4, dtype=torch.int32, device=dev),
+               torch.empty(sz.bytes[1] // 4, dtype=torch.int32, device=dev),
+               torch.empty(sz.bytes[2] // vb, dtype=vt, device=dev)]
+    else:
+        out = [torch.empty(sz.bytes[0] // vb, dtype=vt, device=dev),
+               torch.empty(sz.bytes[1] // 4, dtype=torch.int32, device=dev)]
+    work = torch.empty(max(sz.workspace, 16), dtype=torch.uint8, device=dev)
+    return out, work, sz, s
+
+
+def load_at_table(spmvat):
+    path = os.path.join(ROOT, "paper_2407_00019_amd", "at_table.json")
+    if os.path.exists(path):
+        with open(path) as f:
+            d = json.load(f)
+        t = spmvat.at_table_build(d.get("d", []), d.get("r", []), d.get("feasible"), d.get("c", 1.0))
+        cm = d.get("cost_model")
+        if cm:
+            t.calibrated = 1
+            for f_, per_v in cm["spmv_bps"].items():
+                for v_, buckets in enumerate(per_v):
+                    for b_, val in enumerate(buckets):
+                        t.spmv_bps[int(f_)][v_][b_] = val
+            for f_, buckets in cm["trans_bps"].items():
+                for b_, val in enumerate(buckets):
+                    t.trans_bps[int(f_)][b_] = val
+            t.launch_s = cm.get("launch_s", 0.0)
+        return t, path
+    return spmvat.at_table_build([], [], None, 1.0), None
+
+
+class PathRunner:
+    """Device buffers for one matrix and one value type, allocated once;
+    step() runs the whole path through the C ABI."""
+
+    def __init__(self, spmvat, irp, icol, val, x, label, with_column=True, variants=(0, 1)):
+        import torch
+        self.sp = spmvat
+        self.label = label
+        self.irp, self.icol, self.val, self.x = irp, icol, val, x
+        self.n = irp.numel() - 1
+        self.nnz = icol.numel()
+        self.dev = irp.device
+        self.dtype = spmvat.DTYPE_OF_TORCH[val.dtype]
+        self.vt = val.dtype
+        self.vb = val.element_size()
+        self.xb = x.element_size()
+        self.with_column = with_column
+        self.variants = variants
+        self.work = torch.empty(spmvat.spmv_plan_workspace_bytes(self.n, self.nnz), dtype=torch.uint8, device=self.dev)
+        self.y = torch.empty_like(x)
+        # one plan to size the buffers
+        plan = spmvat.spmv_plan_create(self.n, self.nnz, irp, icol, val, self.dtype, self.work)
+        self.stats = spmvat.spmv_plan_stats(plan)
+        spmvat.spmv_plan_set_limit(plan, 1 << 45)
+        self.buf = {}
+        for f in (spmvat.COO_ROW, spmvat.CCS, spmvat.ELL_ROW) if with_column else (spmvat.COO_ROW, spmvat.ELL_ROW):
+            self.buf[f] = alloc_like(spmvat, plan, f, self.vt, self.dev)
+        if with_column:
+            spmvat.csr_to_ccs(plan, self.buf[spmvat.CCS][0], self.buf[spmvat.CCS][1])
+            torch.cuda.synchronize()
+            self.stats = spmvat.spmv_plan_stats(plan)
+            self.buf[spmvat.COO_COL] = alloc_like(spmvat, plan, spmvat.COO_COL, self.vt, self.dev)
+            self.buf[spmvat.ELL_COL] = alloc_like(spmvat, plan, spmvat.ELL_COL, self.vt, self.dev)
+        spmvat.spmv_plan_destroy(plan)
+        self.ell_w = self.stats.max_row
+        self.ellc_w = self.stats.max_col
+
+    def step(self, T, table=None, spmv_only=False):
+        sp, L = self.sp, self.label
+        plan = T(f"{L}stats", sp.spmv_plan_create, self.n, self.nnz, self.irp, self.icol, self.val, self.dtype,
+                 self.work)
+        sp.spmv_plan_set_limit(plan, 1 << 45)
+        if table is not None:
+            self.decision = sp.at_choose_format(plan, table, 0)
+        T(f"{L}coo_row", sp.csr_to_coo, plan, 0, self.buf[sp.COO_ROW][0])
+        if self.with_column and not spmv_only:
+            T(f"{L}ccs", sp.csr_to_ccs, plan, self.buf[sp.CCS][0], self.buf[sp.CCS][1])
+            T(f"{L}coo_col", sp.csr_to_coo, plan, 1, self.buf[sp.COO_COL][0])
+            T(f"{L}ell_col", sp.csr_to_ell, plan, 1, self.buf[sp.ELL_COL][0])
+        T(f"{L}ell_row", sp.csr_to_ell, plan, 0, self.buf[sp.ELL_ROW][0])
+        for v in self.variants:
+            T(f"{L}spmv_crs{v}", sp.spmv_exec, plan, sp.CRS, v, self.x, self.y)
+        T(f"{L}spmv_ell_row", sp.spmv_exec, plan, sp.ELL_ROW, 0, self.x, self.y)
+        T(f"{L}spmv_coo_row", sp.spmv_exec, plan, sp.COO_ROW, 0, self.x, self.y)
+        if self.with_column and not spmv_only:
+            T(f"{L}spmv_coo_col", sp.spmv_exec, plan, sp.COO_COL, 0, self.x, self.y)
+            T(f"{L}spmv_ell_col", sp.spmv_exec, plan, sp.ELL_COL, 0, self.x, self.y)
+        sp.spmv_plan_destroy(plan)
+
+    def outputs(self, fmt, variant=0):
+        """y of one format (after the steps), for the error report."""
+        sp = self.sp
+        plan = sp.spmv_plan_create(self.n, self.nnz, self.irp, self.icol, self.val, self.dtype, self.work)
+        sp.spmv_plan_set_limit(plan, 1 << 45)
+        if fmt == sp.ELL_ROW:
+            sp.csr_to_ell(plan, 0, self.buf[sp.ELL_ROW][0])
+        sp.spmv_exec(plan, fmt, variant, self.x, self.y)
+        import torch
+        torch.cuda.synchronize()
+        y = self.y.double().cpu().numpy()
+        sp.spmv_plan_destroy(plan)
+        return y
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="stencil27_128", choices=["stencil27_128", "laplace64"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-precision", action="store_true", help="skip the reduced-precision rows")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-oracle SpMV sample")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run one 1 GiB device copy first (reference kernel for the HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
+              "of this path is described in DESIGN.md, not run", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import gen
+    import paper_2407_00019_amd as spmvat
+    if not os.path.exists(spmvat.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    m = gen.stencil27_128() if args.workload == "stencil27_128" else gen.laplace_64x64()
+    cfg_seed = gen.seed_for(2 if args.workload == "stencil27_128" else 1)
+    x64 = gen.x_uniform(m.n, cfg_seed)
+    log(f"[bench] workload {m.name}: n={m.n} nnz={m.nnz} generated in {time.time() - t0:.1f}s")
+    irp = torch.from_numpy(m.irp).to(dev)
+    icol = torch.from_numpy(m.icol).to(dev)
+    val = torch.from_numpy(m.val).to(dev)
+    xd = torch.from_numpy(x64).to(dev)
+    if args.copy_calib:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    mu = m.nnz / m.n
+    wsub = 2
+    while wsub < 64 and wsub < mu:
+        wsub *= 2
+    v_sub = 1 + int(math.log2(wsub))          # explicit lane-group variant of that width
+    runners = [PathRunner(spmvat, irp, icol, val, xd, "", variants=(0, v_sub, 8))]
+    if not args.no_precision:
+        x32 = xd.float()
+        for dt, tag in ((spmvat.F32, "f32"), (spmvat.BF16, "bf16")):
+            v = spmvat.convert_values(val, dt)
+            runners.append(PathRunner(spmvat, irp, icol, v, x32, f"{tag}:", with_column=False, variants=(8,)))
+    table, table_path = load_at_table(spmvat)
+    torch.cuda.synchronize()
+
+    T = Timer()
+
+    def one_step():
+        for r in runners:
+            r.step(T, table if r.label == "" else None)
+        if not args.no_precision:
+            T("f32:convert", spmvat.spmv_convert_values, val, runners[1].val, spmvat.F32)
+            T("bf16:convert", spmvat.spmv_convert_values, val, runners[2].val, spmvat.BF16)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    T.clear()
+    log(f"[bench] warmup done ({args.warmup} steps); timing {args.steps} steps")
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = {k: statistics.mean(v) for k, v in T.results_ms().items()}
+    ms_per_step = 1000.0 * wall / args.steps
+    log(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step")
+
+    n, nnz = m.n, m.nnz
+    r0 = runners[0]
+    w, wc = r0.ell_w, r0.ellc_w
+
+    def gbs(b, t_ms):
+        return b / (t_ms * 1e-3) / 1e9
+
+    per_format = {}
+    spmv_names = {"crs_scalar": ("crs", "spmv_crs0", w), f"crs_subwave{wsub}": ("crs", f"spmv_crs{v_sub}", w),
+                  "crs_stream": ("crs", "spmv_crs8", w),
+                  "ell_row": ("ell_row", "spmv_ell_row", w), "coo_row": ("coo_row", "spmv_coo_row", w),
+                  "coo_col": ("coo_col", "spmv_coo_col", wc), "ell_col": ("ell_col", "spmv_ell_col", wc)}
+    for name, (fmt, key, width) in spmv_names.items():
+        b = spmv_bytes(fmt, n, nnz, width, 8, 8)
+        g = gbs(b, ms[key])
+        per_format[name] = {"us": round(ms[key] * 1e3, 2), "gbs": round(g, 1), "frac": round(g / HBM_PEAK_GBS, 4),
+                            "bytes": int(b)}
+    best = max(per_format, key=lambda k: per_format[k]["gbs"])
+    t_crs0 = ms["spmv_crs0"]
+    t_crs1 = min(ms["spmv_crs8"], ms[f"spmv_crs{v_sub}"])      # the strong CRS kernel
+    transforms = {}
+    for kind, width in (("stats", 0), ("coo_row", 0), ("ccs", 0), ("coo_col", 0), ("ell_row", w), ("ell_col", wc)):
+        b = transform_bytes(kind, n, nnz, width, 8)
+        transforms[kind] = {"us": round(ms[kind] * 1e3, 2), "gbs": round(gbs(b, ms[kind]), 1),
+                            "tt_vs_crs_scalar": round(ms[kind] / t_crs0, 3),
+                            "tt_vs_crs_best": round(ms[kind] / t_crs1, 3), "bytes": int(b)}
+    sp_ell = {"vs_crs_scalar": round(t_crs0 / ms["spmv_ell_row"], 3),
+              "vs_crs_best": round(t_crs1 / ms["spmv_ell_row"], 3)}
+    r_ell = {"vs_crs_scalar": round(sp_ell["vs_crs_scalar"] / (ms["ell_row"] / t_crs0), 4),
+             "vs_crs_best": round(sp_ell["vs_crs_best"] / (ms["ell_row"] / t_crs1), 4)}
+
+    precision = {}
+    if not args.no_precision:
+        import oracle
+        yref = oracle.spmv_crs(n, m.irp, m.icol, m.val, x64)
+        for r, tag, vb in ((runners[1], "f32", 4), (runners[2], "bf16", 2)):
+            entry = {}
+            for fmt, key, code, var in (("crs", "spmv_crs8", spmvat.CRS, 8), ("ell_row", "spmv_ell_row", spmvat.ELL_ROW, 0)):
+                b = spmv_bytes(fmt, n, nnz, w, vb, 4)
+                t_ms = ms[f"{tag}:{key}"]
+                y = r.outputs(code, var)
+                entry[fmt if fmt != "crs" else "crs_stream"] = {
+                    "us": round(t_ms * 1e3, 2), "gbs": round(gbs(b, t_ms), 1), "frac": round(gbs(b, t_ms) / HBM_PEAK_GBS, 4),
+                    "speedup_vs_f64": round(ms[key] / t_ms, 3),
+                    "rel_l2_vs_f64_oracle": float(f"{oracle.rel_l2(y, yref):.3e}")}
+            entry["convert_us"] = round(ms[f"{tag}:convert"] * 1e3, 2)
+            precision[tag] = entry
+
+    head = per_format[best]
+    kernel_names = {"ell_row": "k_spmv_ell_row<double, double>", f"crs_subwave{wsub}": f"k_spmv_crs_vector<double, double, {wsub}>",
+                    "crs_stream": "k_spmv_crs_stream<double, double>",
+                    "crs_scalar": "k_spmv_crs_scalar<double, double>", "coo_row": "k_spmv_coo_row<double, double>",
+                    "coo_col": "k_spmv_coo_col<double, double>", "ell_col": "k_spmv_ell_col<double, double>"}
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        with open(tpath) as f:
+            tj = json.load(f)
+        ent = tj.get("kernels", {}).get(kernel_names[best])
+        if ent and ent.get("source_sha") == kernel_source_sha():
+            traffic = ent.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "kernel": kernel_names[best], "achieved": head["gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": head["frac"], "traffic": traffic,
+                "algorithmic_bytes_per_launch": head["bytes"], "mean_launch_us": head["us"]}
+
+    out = {
+        "metric": METRIC, "value": head["gbs"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": m.name, "n": n, "nnz": nnz, "d_mat": r0.stats.d_mat, "ell_width": w,
+                   "best_format": best, "headline": f"best-format binary64 SpMV, {m.name}"},
+        "roofline": roofline,
+        "per_format": per_format,
+        "transforms": transforms,
+        "sp_ell_row": sp_ell, "r_ell_row": r_ell,
+        "at_decision": {"table": os.path.relpath(table_path, ROOT) if table_path else None,
+                        "d_star": table.d_star if math.isfinite(table.d_star) else "inf",
+                        "choice": spmvat.FORMAT_NAMES[r0.decision[0]] if hasattr(r0, "decision") else None},
+        "precision": precision,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(m, x64, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2407_00019_amd", "csrc"))):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(ROOT, "paper_2407_00019_amd", "csrc", f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(m, x, budget_s):
+    """The CPU oracle as it stands (single-threaded C, binary64) on the same
+    matrix: CRS SpMV repeated for about budget_s seconds; its GB/s uses the
+    same algorithmic bytes as the GPU figure."""
+    import oracle
+    n, nnz = m.n, m.nnz
+    times = []
+    t_end = time.perf_counter() + budget_s
+    while time.perf_counter() < t_end or len(times) < 3:
+        t0 = time.perf_counter()
+        oracle.spmv_crs(n, m.irp, m.icol, m.val, x)
+        times.append(time.perf_counter() - t0)
+    t = statistics.median(times)
+    b = spmv_bytes("crs", n, nnz, 0, 8, 8)
+    # one pass of the oracle's transformations for its own TT figures
+    t0 = time.perf_counter(); oracle.csr_to_coo_row(n, m.irp); t_coo = time.perf_counter() - t0
+    t0 = time.perf_counter(); oracle.csr_to_ell_row(n, m.irp, m.icol, m.val); t_ell = time.perf_counter() - t0
+    t0 = time.perf_counter(); oracle.csr_to_ccs(n, m.irp, m.icol, m.val); t_ccs = time.perf_counter() - t0
+    return {"value": round(b / t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(times)} CRS SpMVs of {m.name} (median {t * 1e3:.1f} ms each) and one pass of "
+                      f"COO-Row / ELL-Row / CCS transformations",
+            "host_cpus": os.cpu_count(),
+            "tt_coo_row": round(t_coo / t, 3), "tt_ell_row": round(t_ell / t, 3), "tt_ccs": round(t_ccs / t, 3)}
+
+
+if __name__ == "__main__":
+    main()

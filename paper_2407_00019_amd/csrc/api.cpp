@@ -59,12 +59,16 @@ spmv_status hip_fail(const spmv_plan* p, hipError_t e) {
         if (e_ != hipSuccess) return hip_fail((p), e_);        \
     } while (0)
 
-// Plan workspace layout: [RowStats | COO carries].
-inline size_t plan_ws_bytes(int64_t nnz) {
-    return round_up(sizeof(RowStats), kAlign) + round_up(coo_carry_bytes(nnz), kAlign);
+// Plan workspace layout: [RowStats | row-statistics partials | COO carries].
+inline size_t stats_bytes() {
+    return round_up(sizeof(RowStats), kAlign) + round_up(row_stats_partial_count() * sizeof(RowStats), kAlign);
 }
+inline size_t plan_ws_bytes(int64_t nnz) { return stats_bytes() + round_up(coo_carry_bytes(nnz), kAlign); }
 inline RowStats* plan_rowstats(const spmv_plan* p) { return reinterpret_cast<RowStats*>(p->work); }
-inline void* plan_carries(const spmv_plan* p) { return p->work + round_up(sizeof(RowStats), kAlign); }
+inline RowStats* plan_partials(const spmv_plan* p) {
+    return reinterpret_cast<RowStats*>(p->work + round_up(sizeof(RowStats), kAlign));
+}
+inline void* plan_carries(const spmv_plan* p) { return p->work + stats_bytes(); }
 
 size_t crs_bytes(const spmv_plan* p) {
     return (size_t)(p->n + 1) * 4 + (size_t)p->nnz * (4 + (size_t)vbytes_of(p->dt));
@@ -78,7 +82,7 @@ CcsWs ccs_ws(int32_t n, int64_t nnz) {
     CcsWs w{};
     size_t o = 0;
     w.cursor = o; o += round_up((size_t)n * 4, kAlign);
-    w.bsum = o;   o += round_up(col_scan_bsum_count(n) * 4, kAlign);
+    w.bsum = o;   o += round_up(col_scan_bsum_count(n) * 8, kAlign);
     const size_t nmid = std::min<size_t>((size_t)n, (size_t)(nnz / (kSortSmall + 1)) + 1);
     const size_t nlong = std::min<size_t>((size_t)n, (size_t)(nnz / (kSortMid + 1)) + 1);
     w.mid = o;    o += round_up(nmid * 4, kAlign);
@@ -106,6 +110,10 @@ int auto_vector_width(const spmv_plan* p) {
     return w;
 }
 
+// Rows up to this length go to the LDS-staged stream kernel under the
+// automatic CRS variant; longer rows would serialise one thread.
+constexpr int32_t kStreamMaxRow = 256;
+
 }  // namespace
 
 // ------------------------------------------------------------------ plan
@@ -131,7 +139,7 @@ SPMV_API spmv_status spmv_plan_create(spmv_plan** plan, int32_t n, int64_t nnz, 
     p->work = static_cast<char*>(plan_work); p->work_bytes = plan_work_bytes;
     hipStream_t s = static_cast<hipStream_t>(stream);
     RowStats rs{};
-    hipError_t e = launch_row_stats(n, nnz, irp, icol, plan_rowstats(p), s);
+    hipError_t e = launch_row_stats(n, nnz, irp, icol, plan_partials(p), plan_rowstats(p), s);
     if (e == hipSuccess) e = hipMemcpyAsync(&rs, plan_rowstats(p), sizeof(rs), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) { delete p; return SPMV_E_HIP; }
@@ -350,14 +358,17 @@ SPMV_API spmv_status spmv_exec(const spmv_plan* p, spmv_format f, int variant, c
     const int dt = (int)p->dt;
     const int64_t ybytes = (int64_t)p->n * xbytes_of(p->dt);
     switch (f) {
-        case SPMV_CRS:
-            if (variant < 0 || variant > 7) return SPMV_E_ARG;
+        case SPMV_CRS: {
+            if (variant < 0 || variant > 8) return SPMV_E_ARG;
+            const bool stream = variant == 8 || (variant == 1 && p->st.max_row <= kStreamMaxRow);
             if (variant == 0) HIP_TRY(p, launch_spmv_crs_scalar(dt, p->n, p->irp, p->icol, p->val, x, y, s));
+            else if (stream) HIP_TRY(p, launch_spmv_crs_stream(dt, p->n, p->irp, p->icol, p->val, x, y, s));
             else {
                 const int w = variant == 1 ? auto_vector_width(p) : (1 << (variant - 1));
                 HIP_TRY(p, launch_spmv_crs_vector(dt, w, p->n, p->irp, p->icol, p->val, x, y, s));
             }
             return SPMV_OK;
+        }
         case SPMV_COO_ROW:
             if (variant != 0) return SPMV_E_ARG;
             if (!p->has_coo_row) return SPMV_E_NOT_READY;

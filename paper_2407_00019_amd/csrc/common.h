@@ -36,6 +36,19 @@ __device__ __forceinline__ float widen(f16_t v) {
     return (float)h;
 }
 
+// Streaming loads that should not displace the x vector from the caches.
+template <typename T> __device__ __forceinline__ T ld_nt(const T* p) { return __builtin_nontemporal_load(p); }
+template <> __device__ __forceinline__ bf16_t ld_nt(const bf16_t* p) {
+    bf16_t r;
+    r.bits = __builtin_nontemporal_load(&p->bits);
+    return r;
+}
+template <> __device__ __forceinline__ f16_t ld_nt(const f16_t* p) {
+    f16_t r;
+    r.bits = __builtin_nontemporal_load(&p->bits);
+    return r;
+}
+
 // Raw element types used when values are only moved (transformations).
 template <int B> struct raw_of;
 template <> struct raw_of<8> { using type = uint64_t; };

@@ -5,6 +5,10 @@
 //  CRS scalar     one thread per row (the plain CRS loop).
 //  CRS vector     a power-of-two lane group per row, coalesced row loads,
 //                 butterfly reduction inside the group.
+//  CRS stream     a workgroup takes 256 rows; their entries, contiguous in
+//                 CRS, are read coalesced in chunks and their products kept
+//                 in LDS; each row is then summed by its own thread in
+//                 storage order.
 //  ELL-Row        Fig. 3: thread per row, slot loop inside, slot-major loads
 //                 coalesced across the wave; no reduction step.
 //  ELL-Column     thread per column, y(row) += val * x(col) with atomics.
@@ -52,6 +56,35 @@ k_spmv_crs_vector(int n, const int* __restrict__ irp, const int* __restrict__ ic
     if (lane == 0 && row < n) y[row] = s;
 }
 
+constexpr int kStreamCap = 2048;   // products staged in LDS per chunk
+
+template <typename V, typename X>
+__global__ void __launch_bounds__(kBlock)
+k_spmv_crs_stream(int n, const int* __restrict__ irp, const int* __restrict__ icol, const V* __restrict__ val,
+                  const X* __restrict__ x, X* __restrict__ y) {
+    __shared__ X prod[kStreamCap];
+    __shared__ int sp[kBlock + 1];
+    const int r0 = (int)xcd_block(blockIdx.x, gridDim.x) * kBlock;
+    const int rows = min(kBlock, n - r0);
+    const int t = threadIdx.x;
+    for (int c = t; c <= rows; c += kBlock) sp[c] = irp[r0 + c];
+    __syncthreads();
+    const int end = sp[rows];
+    const int a = t < rows ? sp[t] : end, b = t < rows ? sp[t + 1] : end;
+    X s = 0;
+    for (int c0 = sp[0]; c0 < end; c0 += kStreamCap) {
+        const int cl = min(kStreamCap, end - c0);
+#pragma unroll 4
+        for (int q = t; q < cl; q += kBlock)
+            prod[q] = (X)widen(ld_nt(&val[c0 + q])) * x[ld_nt(&icol[c0 + q])];
+        __syncthreads();
+        const int lo = max(a, c0), hi = min(b, c0 + cl);
+        for (int p = lo; p < hi; ++p) s += prod[p - c0];
+        __syncthreads();
+    }
+    if (t < rows) y[r0 + t] = s;
+}
+
 // ------------------------------------------------------------- ELL
 
 template <typename V, typename X>
@@ -62,8 +95,9 @@ k_spmv_ell_row(int n, int width, const V* __restrict__ ev, const int* __restrict
     if (i >= n) return;
     X s = 0;
     size_t off = (size_t)i;
-#pragma unroll 4
-    for (int k = 0; k < width; ++k, off += (size_t)n) s += (X)widen(ev[off]) * x[ec[off]];
+#pragma unroll 8
+    for (int k = 0; k < width; ++k, off += (size_t)n)
+        s += (X)widen(ld_nt(&ev[off])) * x[ld_nt(&ec[off])];
     y[i] = s;
 }
 
@@ -237,6 +271,13 @@ static inline unsigned grid_for(int64_t items, int per_block) {
         case 2: { typedef bf16_t V; typedef float X; CALL; break; }  \
         default: { typedef f16_t V; typedef float X; CALL; break; }  \
     }
+
+hipError_t launch_spmv_crs_stream(int dtype, int n, const int* irp, const int* icol, const void* val,
+                                  const void* x, void* y, hipStream_t s) {
+    SPMV_DISPATCH(dtype, hipLaunchKernelGGL((k_spmv_crs_stream<V, X>), dim3(grid_for(n, kBlock)), dim3(kBlock),
+                                            0, s, n, irp, icol, (const V*)val, (const X*)x, (X*)y));
+    return hipGetLastError();
+}
 
 hipError_t launch_spmv_crs_scalar(int dtype, int n, const int* irp, const int* icol, const void* val,
                                   const void* x, void* y, hipStream_t s) {

@@ -105,9 +105,10 @@ hipError_t launch_col_count(int64_t nnz, const int* icol, int* cnt, hipStream_t 
 constexpr int kScanPer = kScanTile / kBlock;   // 16 counts per thread
 
 __global__ void __launch_bounds__(kBlock)
-k_scan_reduce(int n, const int* __restrict__ cnt, int* __restrict__ bsum, int* __restrict__ mid_list,
-              int* __restrict__ long_list, ColSummary* __restrict__ sum) {
+k_scan_reduce(int n, const int* __restrict__ cnt, int* __restrict__ bsum, int* __restrict__ bmax,
+              int* __restrict__ mid_list, int* __restrict__ long_list, ColSummary* __restrict__ sum) {
     __shared__ int sh[kBlock / kWave];
+    __shared__ int shm[kBlock / kWave];
     const int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
     int s = 0, mx = 0;
 #pragma unroll
@@ -125,26 +126,41 @@ k_scan_reduce(int n, const int* __restrict__ cnt, int* __restrict__ bsum, int* _
     }
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, kWave));
-    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(&sum->max_len, mx);
+    if ((threadIdx.x & (kWave - 1)) == 0) shm[threadIdx.x / kWave] = mx;
     int total;
-    block_excl_scan(s, sh, total);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+    block_excl_scan(s, sh, total);   // its barriers also publish shm
+    if (threadIdx.x == 0) {
+        bsum[blockIdx.x] = total;
+        int m = shm[0];
+        for (int w = 1; w < kBlock / kWave; ++w) m = max(m, shm[w]);
+        bmax[blockIdx.x] = m;
+    }
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_scan_top(int nb, int n, int* __restrict__ bsum, int* __restrict__ ccp, ColSummary* __restrict__ sum) {
+k_scan_top(int nb, int n, int* __restrict__ bsum, const int* __restrict__ bmax, int* __restrict__ ccp,
+           ColSummary* __restrict__ sum) {
     __shared__ int sh[kBlock / kWave];
-    int carry = 0;
+    __shared__ int shm[kBlock / kWave];
+    int carry = 0, mx = 0;
     for (int base = 0; base < nb; base += kBlock) {
         const int j = base + threadIdx.x;
         const int v = j < nb ? bsum[j] : 0;
+        if (j < nb) mx = max(mx, bmax[j]);
         int total;
         const int ex = block_excl_scan(v, sh, total);
         if (j < nb) bsum[j] = carry + ex;
         carry += total;
     }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0) shm[threadIdx.x / kWave] = mx;
+    __syncthreads();
     if (threadIdx.x == 0) {
+        int m = shm[0];
+        for (int w = 1; w < kBlock / kWave; ++w) m = max(m, shm[w]);
         sum->total = carry;
+        sum->max_len = m;
         ccp[n] = carry;
     }
 }
@@ -179,10 +195,11 @@ size_t col_scan_bsum_count(int n) { return (size_t)((n + kScanTile - 1) / kScanT
 hipError_t launch_col_scan(int n, const int* cnt, int* ccp, int* cursor, int* bsum, int* mid_list,
                            int* long_list, ColSummary* sum, hipStream_t s) {
     const int nb = (int)col_scan_bsum_count(n);
+    int* bmax = bsum + nb;
     hipError_t e = hipMemsetAsync(sum, 0, sizeof(ColSummary), s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, n, cnt, bsum, mid_list, long_list, sum);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, nb, n, bsum, ccp, sum);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, n, cnt, bsum, bmax, mid_list, long_list, sum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, nb, n, bsum, bmax, ccp, sum);
     hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, s, n, cnt, bsum, ccp, cursor);
     return hipGetLastError();
 }
@@ -216,9 +233,9 @@ hipError_t launch_ccs_scatter(int n, const int* irp, const int* icol, int* curso
 
 // --------------------------------------- Phase I: per-column key sort
 // Keys are unique (one per CRS position), so sorting them by value gives
-// the one stable order.  Columns of up to kSortSmall entries: one thread,
-// insertion sort in place (the scatter leaves them nearly sorted).  Up to
-// kSortMid: one workgroup, bitonic sort in LDS.  Longer: chunks sorted in
+// the one stable order.  Columns of up to kSortSmall entries: ranked by a
+// workgroup in LDS (below).  Up to kSortMid: one workgroup per column,
+// bitonic sort in LDS.  Longer: chunks sorted in
 // LDS, then merge passes in global memory.  Every path ends by emitting
 // irow_t[q] = row and val_t[q] = val[position] for its column.
 
@@ -229,29 +246,62 @@ __device__ __forceinline__ void emit(int q, u64 key, const R* __restrict__ val, 
     val_t[q] = val[key >> 32];
 }
 
+// Columns of up to kSortSmall entries: a workgroup takes 256 consecutive
+// columns, stages the keys of as many whole columns as fit (kRankCap) in LDS,
+// and gives each key its rank among the keys of its column (a linear count;
+// lanes of one column read the same LDS words, which broadcast).  The rank is
+// the key's final offset in its column, so it is emitted straight away.
+constexpr int kRankCap = 6144;
+
 template <typename R>
 __global__ void __launch_bounds__(kBlock)
-k_sort_small(int n, const int* __restrict__ ccp, u64* __restrict__ keys, const R* __restrict__ val,
-             int* __restrict__ irow_t, R* __restrict__ val_t) {
-    const int j = (int)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (j >= n) return;
-    const int s = ccp[j], e = ccp[j + 1];
-    if (e - s > kSortSmall || e == s) return;
-    u64 prev = keys[s];
-    for (int a = s + 1; a < e; ++a) {
-        const u64 k = keys[a];
-        if (k > prev) { prev = k; continue; }
-        keys[a] = prev;
-        int b = a - 2;
-        while (b >= s) {
-            const u64 t = keys[b];
-            if (t < k) break;
-            keys[b + 1] = t;
-            --b;
+k_sort_rank(int n, const int* __restrict__ ccp, const u64* __restrict__ keys, const R* __restrict__ val,
+            int* __restrict__ irow_t, R* __restrict__ val_t) {
+    __shared__ int sp[kBlock + 1];
+    __shared__ unsigned long long s_long[kBlock / kWave];
+    __shared__ u64 sk[kRankCap];
+    const int j0 = (int)xcd_block(blockIdx.x, gridDim.x) * kBlock;
+    const int cols = min(kBlock, n - j0);
+    const int t = threadIdx.x;
+    for (int c = t; c <= cols; c += kBlock) sp[c] = ccp[j0 + c];
+    __syncthreads();
+    // columns left to the workgroup and multi-pass sorts, as a 256-bit mask
+    const bool lng = t < cols && (sp[t + 1] - sp[t]) > kSortSmall;
+    const unsigned long long m = __ballot(lng);
+    if ((t & (kWave - 1)) == 0) s_long[t / kWave] = m;
+    __syncthreads();
+
+    int c0 = 0;
+    while (c0 < cols) {
+        // first long column at or after c0 (cols if none)
+        int fl = cols;
+        for (int w = c0 / kWave; w < kBlock / kWave; ++w) {
+            unsigned long long word = s_long[w];
+            if (w == c0 / kWave) word &= ~0ull << (c0 % kWave);
+            if (word) { fl = min(cols, w * kWave + __ffsll((long long)word) - 1); break; }
         }
-        keys[b + 1] = k;
+        if (fl == c0) { ++c0; continue; }
+        // largest c1 in (c0, fl] whose keys fit in LDS; one short column always fits
+        int lo = c0 + 1, hi = fl;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sp[mid] - sp[c0] <= kRankCap) lo = mid; else hi = mid - 1;
+        }
+        const int c1 = lo;
+        const int base = sp[c0], span = sp[c1] - base;
+        for (int q = t; q < span; q += kBlock) sk[q] = keys[base + q];
+        __syncthreads();
+        for (int q = t; q < span; q += kBlock) {
+            const u64 key = sk[q];
+            const int c = last_le(sp, c0, c1 - 1, base + q);
+            const int s = sp[c] - base, e = sp[c + 1] - base;
+            int rank = 0;
+            for (int k2 = s; k2 < e; ++k2) rank += sk[k2] < key;
+            emit<R>(sp[c] + rank, key, val, irow_t, val_t);
+        }
+        __syncthreads();
+        c0 = c1;
     }
-    for (int q = s; q < e; ++q) emit<R>(q, keys[q], val, irow_t, val_t);
 }
 
 // Bitonic sort of up to kSortMid keys in LDS (pad with all-ones).
@@ -367,7 +417,7 @@ template <typename R>
 static hipError_t sort_small_t(int n, const int* ccp, u64* keys, const void* val, int* irow_t, void* val_t,
                                hipStream_t s) {
     unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_sort_small<R>, dim3(blocks), dim3(kBlock), 0, s, n, ccp, keys,
+    hipLaunchKernelGGL(k_sort_rank<R>, dim3(blocks), dim3(kBlock), 0, s, n, ccp, keys,
                        (const R*)val, irow_t, (R*)val_t);
     return hipGetLastError();
 }
@@ -437,29 +487,68 @@ hipError_t launch_ccs_sort_long(int start, int len, u64* keys, u64* tmp, const v
 }
 
 // ------------------------------------------------------------- ELL pack
-// Thread per line, a chunk of 64 slots per grid row.  Stores of slot k for
-// 64 consecutive lines are contiguous (slot-major layout); a line's stored
-// entries are read in order.  Padding: value bits 0 (+0.0), index = line.
+// Workgroup tile = 64 consecutive lines x 32 slots.  The tile's stored
+// entries are read contiguously (a line's entries are consecutive, and so
+// are consecutive lines'), transposed through LDS, and written one slot plane
+// at a time: 64 consecutive lines of slot k are 64 consecutive elements of
+// the slot-major arrays.  Padding: value bits 0 (+0.0), index = line.
 
-constexpr int kEllSlotChunk = 64;
+constexpr int kEllRows = 64;
+constexpr int kEllSlots = 32;
+constexpr int kEllPitch = kEllRows + 1;   // pads LDS rows against bank conflicts
 
 template <typename R>
 __global__ void __launch_bounds__(kBlock)
 k_ell_pack(int n, int width, const int* __restrict__ ptr, const int* __restrict__ idx, const R* __restrict__ val,
            R* __restrict__ ev, int* __restrict__ ei) {
-    const int i = (int)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const int a = ptr[i], len = ptr[i + 1] - a;
-    const int k0 = blockIdx.y * kEllSlotChunk;
-    const int k1 = min(width, k0 + kEllSlotChunk);
-    size_t off = (size_t)k0 * (size_t)n + (size_t)i;
-    for (int k = k0; k < k1; ++k, off += (size_t)n) {
-        if (k < len) {
-            ev[off] = val[a + k];
-            ei[off] = idx[a + k];
-        } else {
-            ev[off] = (R)0;
-            ei[off] = i;
+    __shared__ R tv[kEllSlots * kEllPitch];
+    __shared__ int ti[kEllSlots * kEllPitch];
+    __shared__ int pre[kEllRows + 1];
+    __shared__ int sa[kEllRows];
+    __shared__ int scnt[kEllRows];
+    const int t = threadIdx.x;
+    const int i0 = (int)xcd_block(blockIdx.x, gridDim.x) * kEllRows;
+    const int rows = min(kEllRows, n - i0);
+    const int k0 = blockIdx.y * kEllSlots;
+    const int kw = min(kEllSlots, width - k0);
+    if (t < kEllRows) {
+        int cnt = 0;
+        if (t < rows) {
+            const int a = ptr[i0 + t];
+            cnt = min(max(ptr[i0 + t + 1] - a - k0, 0), kw);
+            sa[t] = a + k0;
+        }
+        scnt[t] = cnt;
+        // exclusive scan of the counts over the first wave
+        int x = cnt;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int y = __shfl_up(x, off, kWave);
+            if (t >= off) x += y;
+        }
+        pre[t] = x - cnt;
+        if (t == kEllRows - 1) pre[kEllRows] = x;
+    }
+    __syncthreads();
+    const int total = pre[kEllRows];
+    for (int f = t; f < total; f += kBlock) {
+        const int r = last_le(pre, 0, rows - 1, f);
+        const int k = f - pre[r];
+        tv[k * kEllPitch + r] = val[sa[r] + k];
+        ti[k * kEllPitch + r] = idx[sa[r] + k];
+    }
+    __syncthreads();
+    const int r = t & (kEllRows - 1);
+    if (r < rows) {
+        for (int k = t / kEllRows; k < kw; k += kBlock / kEllRows) {
+            const size_t off = (size_t)(k0 + k) * (size_t)n + (size_t)(i0 + r);
+            if (k < scnt[r]) {
+                ev[off] = tv[k * kEllPitch + r];
+                ei[off] = ti[k * kEllPitch + r];
+            } else {
+                ev[off] = (R)0;
+                ei[off] = i0 + r;
+            }
         }
     }
 }
@@ -467,7 +556,7 @@ k_ell_pack(int n, int width, const int* __restrict__ ptr, const int* __restrict_
 template <typename R>
 static hipError_t ell_pack_t(int n, int width, const int* ptr, const int* idx, const void* val, void* ev,
                              int* ei, hipStream_t s) {
-    dim3 grid((unsigned)((n + kBlock - 1) / kBlock), (unsigned)((width + kEllSlotChunk - 1) / kEllSlotChunk));
+    dim3 grid((unsigned)((n + kEllRows - 1) / kEllRows), (unsigned)((width + kEllSlots - 1) / kEllSlots));
     hipLaunchKernelGGL(k_ell_pack<R>, grid, dim3(kBlock), 0, s, n, width, ptr, idx, (const R*)val, (R*)ev, ei);
     return hipGetLastError();
 }

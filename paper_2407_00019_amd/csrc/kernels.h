@@ -24,7 +24,7 @@ struct ColSummary {
     int32_t n_long;       // columns with len > kSortMid
 };
 
-constexpr int kSortSmall = 256;   // sorted by one thread in place
+constexpr int kSortSmall = 512;   // ranked by a workgroup in LDS
 constexpr int kSortMid = 8192;    // sorted by one workgroup in LDS
 constexpr int kScanTile = 4096;   // counts per workgroup in the column scan
 
@@ -34,15 +34,16 @@ constexpr int kCooPerThread = 8;
 constexpr int kCooTile = 256 * kCooPerThread;
 
 // ---- statistics
-hipError_t launch_row_stats(int n, int64_t nnz, const int* irp, const int* icol, RowStats* out,
-                            hipStream_t s);
+size_t row_stats_partial_count();
+hipError_t launch_row_stats(int n, int64_t nnz, const int* irp, const int* icol, RowStats* partial,
+                            RowStats* out, hipStream_t s);
 
 // ---- transformations
 hipError_t launch_expand_ptr(int n, const int* ptr, int* out, hipStream_t s);
 hipError_t launch_col_count(int64_t nnz, const int* icol, int* cnt, hipStream_t s);
 hipError_t launch_col_scan(int n, const int* cnt, int* ccp, int* cursor, int* bsum,
                            int* mid_list, int* long_list, ColSummary* sum, hipStream_t s);
-size_t col_scan_bsum_count(int n);
+size_t col_scan_bsum_count(int n);   // per array; the scan needs two (sums, maxima)
 hipError_t launch_ccs_scatter(int n, const int* irp, const int* icol, int* cursor,
                               unsigned long long* keys, hipStream_t s);
 hipError_t launch_ccs_sort_small(int n, const int* ccp, unsigned long long* keys, const void* val,
@@ -60,6 +61,8 @@ hipError_t launch_ell_pack(int n, int width, const int* ptr, const int* idx, con
 // ---- SpMV (dtype: 0 F64, 1 F32, 2 BF16, 3 F16)
 hipError_t launch_fill_zero(void* y, int64_t bytes, hipStream_t s);
 hipError_t launch_spmv_crs_scalar(int dtype, int n, const int* irp, const int* icol, const void* val,
+                                  const void* x, void* y, hipStream_t s);
+hipError_t launch_spmv_crs_stream(int dtype, int n, const int* irp, const int* icol, const void* val,
                                   const void* x, void* y, hipStream_t s);
 hipError_t launch_spmv_crs_vector(int dtype, int width, int n, const int* irp, const int* icol,
                                   const void* val, const void* x, void* y, hipStream_t s);

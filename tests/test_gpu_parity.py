@@ -72,8 +72,9 @@ def run_gpu_all(m, x64):
     (out["ellc_val"], out["ellc_row"]), out["ellc_w"] = plan.to_ell(column_wise=True)
     out["max_col"] = plan.stats.max_col
     ys = {}
-    for fmt, var in [(spmvat.CRS, 0), (spmvat.CRS, 1), (spmvat.CRS, 2), (spmvat.CRS, 4), (spmvat.CRS, 7),
-                     (spmvat.COO_ROW, 0), (spmvat.ELL_ROW, 0), (spmvat.COO_COL, 0), (spmvat.ELL_COL, 0)]:
+    for fmt, var in [(spmvat.CRS, 0), (spmvat.CRS, 1), (spmvat.CRS, 2), (spmvat.CRS, 4), (spmvat.CRS, 6),
+                     (spmvat.CRS, 7), (spmvat.CRS, 8), (spmvat.COO_ROW, 0), (spmvat.ELL_ROW, 0),
+                     (spmvat.COO_COL, 0), (spmvat.ELL_COL, 0)]:
         ys[(fmt, var)] = host(plan.spmv(fmt, xd, variant=var))
     out["y"] = ys
     out = {k: (host(v) if hasattr(v, "cpu") else v) for k, v in out.items()}
@@ -205,8 +206,8 @@ def test_powerlaw_full_size():
     assert np.array_equal(bits(host(cv)), bits(o_cv))
     assert np.array_equal(host(cr), o_cr)
     yref = oracle.spmv_crs(m.n, m.irp, m.icol, m.val, x)
-    for fmt, var in [(spmvat.CRS, 0), (spmvat.CRS, 1), (spmvat.COO_ROW, 0), (spmvat.COO_COL, 0),
-                     (spmvat.ELL_COL, 0)]:
+    for fmt, var in [(spmvat.CRS, 0), (spmvat.CRS, 1), (spmvat.CRS, 5), (spmvat.CRS, 8), (spmvat.COO_ROW, 0),
+                     (spmvat.COO_COL, 0), (spmvat.ELL_COL, 0)]:
         y = host(plan.spmv(fmt, xd, variant=var))
         assert oracle.rel_l2(y, yref) <= TOL64, (fmt, var)
     plan.close()
