@@ -16,7 +16,8 @@
 //                 8 consecutive entries per thread, a segmented scan across
 //                 the workgroup, workgroup carries folded in by a second
 //                 kernel in workgroup order -- deterministic.
-//  COO-Column     Fig. 1: entries in column order, y(row) += ... with atomics.
+//  COO-Column     Fig. 1: chunks of entries in column order; inside a
+//                 chunk one lane per column, y(row) += ... with atomics.
 #include "common.h"
 #include "kernels.h"
 
@@ -117,13 +118,83 @@ k_spmv_ell_col(int n, int width, const V* __restrict__ ev, const int* __restrict
 
 // ------------------------------------------------------------- COO
 
+// COO-Column: a workgroup takes a contiguous chunk of kCooColTile entries
+// (the entry-range partition of Fig. 1), stages rows and values in LDS,
+// finds where each column starts inside the chunk, and gives each lane one
+// column to walk.  Entries of a column are in row order, so at every step
+// the lanes of a wave add into nearby rows and the atomics coalesce; a
+// column cut by the chunk boundary is simply added from both chunks.
+constexpr int kCooColTile = 2048;
+constexpr int kCooColPer = kCooColTile / kBlock;   // 8 entries per thread for the head scan
+
 template <typename V, typename X>
 __global__ void __launch_bounds__(kBlock)
 k_spmv_coo_col(int64_t nnz, const int* __restrict__ jcol, const int* __restrict__ irow_t,
                const V* __restrict__ val_t, const X* __restrict__ x, X* __restrict__ y) {
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nnz; q += stride)
-        atomic_add(&y[irow_t[q]], (X)widen(val_t[q]) * x[jcol[q]]);
+    __shared__ int s_row[kCooColTile];
+    __shared__ V s_val[kCooColTile];
+    __shared__ int s_head[kCooColTile + 1];
+    __shared__ int s_col[kCooColTile];
+    __shared__ int s_w[kBlock / kWave];
+    const int64_t t0 = (int64_t)blockIdx.x * kCooColTile;
+    const int cnt = (int)min((int64_t)kCooColTile, nnz - t0);
+    const int t = threadIdx.x;
+    for (int q = t; q < cnt; q += kBlock) {
+        s_row[q] = irow_t[t0 + q];
+        s_val[q] = val_t[t0 + q];
+    }
+    // column starts inside the chunk: thread t looks at entries 8t .. 8t+7
+    int prev = (t0 + t * kCooColPer > 0 && t * kCooColPer < cnt) ? jcol[t0 + t * kCooColPer - 1] : -1;
+    if (t0 == 0 && t == 0) prev = -1;
+    int cols[kCooColPer];
+    int heads = 0;
+#pragma unroll
+    for (int e = 0; e < kCooColPer; ++e) {
+        const int q = t * kCooColPer + e;
+        cols[e] = q < cnt ? jcol[t0 + q] : -1;
+        const bool h = q < cnt && (q == 0 || cols[e] != prev);
+        heads += h;
+        prev = q < cnt ? cols[e] : prev;
+    }
+    // exclusive scan of the head counts over the workgroup
+    const int lane = t & (kWave - 1), w = t / kWave;
+    int xs = heads;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int yv = __shfl_up(xs, off, kWave);
+        if (lane >= off) xs += yv;
+    }
+    if (lane == kWave - 1) s_w[w] = xs;
+    __syncthreads();
+    int pre = 0, nh = 0;
+#pragma unroll
+    for (int k = 0; k < kBlock / kWave; ++k) {
+        pre += k < w ? s_w[k] : 0;
+        nh += s_w[k];
+    }
+    int pos = pre + xs - heads;
+    int last = (t * kCooColPer > 0 && t * kCooColPer < cnt) ? jcol[t0 + t * kCooColPer - 1] : -1;
+    if (t == 0) last = -1;
+#pragma unroll
+    for (int e = 0; e < kCooColPer; ++e) {
+        const int q = t * kCooColPer + e;
+        if (q < cnt && (q == 0 || cols[e] != last)) {
+            s_head[pos] = q;
+            s_col[pos] = cols[e];
+            ++pos;
+        }
+        if (q < cnt) last = cols[e];
+    }
+    if (t == 0) s_head[nh] = cnt;
+    __syncthreads();
+    for (int h = t; h < nh; h += kBlock) {
+        const X xj = x[s_col[h]];
+        const int e = s_head[h + 1];
+        for (int q = s_head[h]; q < e; ++q) {
+            const X v = (X)widen(s_val[q]);
+            atomic_add(&y[s_row[q]], v * xj);
+        }
+    }
 }
 
 // Eight consecutive elements through 16-byte loads (the caller guarantees
@@ -327,9 +398,8 @@ hipError_t launch_spmv_ell_col(int dtype, int n, int width, const void* ev, cons
 
 hipError_t launch_spmv_coo_col(int dtype, int64_t nnz, const int* jcol, const int* irow_t, const void* val_t,
                                const void* x, void* y, hipStream_t s) {
-    int64_t blocks = (nnz + kBlock - 1) / kBlock;
-    if (blocks > 16384) blocks = 16384;
-    if (blocks < 1) blocks = 1;
+    const int64_t blocks = (nnz + kCooColTile - 1) / kCooColTile;
+    if (blocks == 0) return hipSuccess;
     SPMV_DISPATCH(dtype, hipLaunchKernelGGL((k_spmv_coo_col<V, X>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
                                             nnz, jcol, irow_t, (const V*)val_t, (const X*)x, (X*)y));
     return hipGetLastError();

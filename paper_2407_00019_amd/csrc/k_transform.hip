@@ -49,19 +49,30 @@ __device__ __forceinline__ void load_ptr_tile(const int* __restrict__ ptr, int r
 }
 
 // -------------------------------------------------------- ptr expansion
-// Workgroup = 256 consecutive lines; its positions [ptr[r0], ptr[r0+256])
-// are walked with a stride of 256 (coalesced stores), each position's line
-// found by binary search in the LDS copy of the pointer slice.
+// Workgroup = 256 consecutive lines.  Each lane writes its own line index
+// over its positions into an LDS image of the tile's slice of the output,
+// which is then stored with coalesced writes.
+
+constexpr int kExpandCap = 8192;
 
 __global__ void __launch_bounds__(kBlock)
 k_expand_ptr(int n, const int* __restrict__ ptr, int* __restrict__ out) {
     __shared__ int sp[kBlock + 1];
+    __shared__ int so[kExpandCap];
     const int r0 = (int)xcd_block(blockIdx.x, gridDim.x) * kBlock;
     const int rows = min(kBlock, n - r0);
+    const int t = threadIdx.x;
     load_ptr_tile(ptr, r0, rows, sp);
-    const int q1 = sp[rows];
-    for (int q = sp[0] + threadIdx.x; q < q1; q += kBlock)
-        out[q] = r0 + last_le(sp, 0, rows - 1, q);
+    const int end = sp[rows];
+    const int a = t < rows ? sp[t] : end, b = t < rows ? sp[t + 1] : end;
+    for (int c0 = sp[0]; c0 < end; c0 += kExpandCap) {
+        const int cl = min(kExpandCap, end - c0);
+        const int lo = max(a, c0), hi = min(b, c0 + cl);
+        for (int p = lo; p < hi; ++p) so[p - c0] = r0 + t;
+        __syncthreads();
+        for (int q = t; q < cl; q += kBlock) out[c0 + q] = so[q];
+        __syncthreads();
+    }
 }
 
 hipError_t launch_expand_ptr(int n, const int* ptr, int* out, hipStream_t s) {
@@ -71,28 +82,48 @@ hipError_t launch_expand_ptr(int n, const int* ptr, int* out, hipStream_t s) {
 }
 
 // ------------------------------------------------ Phase I: column counts
+// and the scatter.  Both walk a tile of 256 rows with one row per lane:
+// the tile's column indices (contiguous in CRS) are staged in LDS with
+// coalesced loads, then every lane steps through its own row.  For banded
+// and stencil matrices the lanes of a wave then touch consecutive columns at
+// each step, so a wave's atomics coalesce into a few cache lines.
 
+constexpr int kRowTileCap = 8192;   // column indices staged per pass
+
+template <bool kScatter>
 __global__ void __launch_bounds__(kBlock)
-k_col_count(int64_t nnz, const int* __restrict__ icol, int* __restrict__ cnt) {
-    const int64_t nv = nnz >> 2;
-    const int4* ic4 = reinterpret_cast<const int4*>(icol);
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nv; q += stride) {
-        int4 c = ic4[q];
-        atomicAdd(&cnt[c.x], 1);
-        atomicAdd(&cnt[c.y], 1);
-        atomicAdd(&cnt[c.z], 1);
-        atomicAdd(&cnt[c.w], 1);
+k_col_walk(int n, const int* __restrict__ irp, const int* __restrict__ icol, int* __restrict__ counter,
+           u64* __restrict__ keys) {
+    __shared__ int sp[kBlock + 1];
+    __shared__ int sc[kRowTileCap];
+    const int r0 = (int)xcd_block(blockIdx.x, gridDim.x) * kBlock;
+    const int rows = min(kBlock, n - r0);
+    const int t = threadIdx.x;
+    for (int c = t; c <= rows; c += kBlock) sp[c] = irp[r0 + c];
+    __syncthreads();
+    const int end = sp[rows];
+    const int a = t < rows ? sp[t] : end, b = t < rows ? sp[t + 1] : end;
+    for (int c0 = sp[0]; c0 < end; c0 += kRowTileCap) {
+        const int cl = min(kRowTileCap, end - c0);
+        for (int q = t; q < cl; q += kBlock) sc[q] = icol[c0 + q];
+        __syncthreads();
+        const int lo = max(a, c0), hi = min(b, c0 + cl);
+        for (int p = lo; p < hi; ++p) {
+            const int c = sc[p - c0];
+            if (kScatter) {
+                const int slot = atomicAdd(&counter[c], 1);
+                keys[slot] = ((u64)(uint32_t)p << 32) | (uint32_t)(r0 + t);
+            } else {
+                atomicAdd(&counter[c], 1);
+            }
+        }
+        __syncthreads();
     }
-    if (blockIdx.x == 0)
-        for (int64_t p = (nv << 2) + threadIdx.x; p < nnz; p += kBlock) atomicAdd(&cnt[icol[p]], 1);
 }
 
-hipError_t launch_col_count(int64_t nnz, const int* icol, int* cnt, hipStream_t s) {
-    int64_t blocks = ((nnz >> 2) + kBlock - 1) / kBlock;
-    if (blocks > 8192) blocks = 8192;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_col_count, dim3((unsigned)blocks), dim3(kBlock), 0, s, nnz, icol, cnt);
+hipError_t launch_col_count(int n, const int* irp, const int* icol, int* cnt, hipStream_t s) {
+    unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_col_walk<false>, dim3(blocks), dim3(kBlock), 0, s, n, irp, icol, cnt, nullptr);
     return hipGetLastError();
 }
 
@@ -209,25 +240,10 @@ hipError_t launch_col_scan(int n, const int* cnt, int* ccp, int* cursor, int* bs
 // through its cursor and stores the key (q << 32 | r) there.  Slot order
 // inside a column depends on scheduling; the sort below fixes it.
 
-__global__ void __launch_bounds__(kBlock)
-k_ccs_scatter(int n, const int* __restrict__ irp, const int* __restrict__ icol, int* __restrict__ cursor,
-              u64* __restrict__ keys) {
-    __shared__ int sp[kBlock + 1];
-    const int r0 = (int)xcd_block(blockIdx.x, gridDim.x) * kBlock;
-    const int rows = min(kBlock, n - r0);
-    load_ptr_tile(irp, r0, rows, sp);
-    const int q1 = sp[rows];
-    for (int q = sp[0] + threadIdx.x; q < q1; q += kBlock) {
-        const int r = r0 + last_le(sp, 0, rows - 1, q);
-        const int slot = atomicAdd(&cursor[icol[q]], 1);
-        keys[slot] = ((u64)(uint32_t)q << 32) | (uint32_t)r;
-    }
-}
-
 hipError_t launch_ccs_scatter(int n, const int* irp, const int* icol, int* cursor, u64* keys,
                               hipStream_t s) {
     unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_ccs_scatter, dim3(blocks), dim3(kBlock), 0, s, n, irp, icol, cursor, keys);
+    hipLaunchKernelGGL(k_col_walk<true>, dim3(blocks), dim3(kBlock), 0, s, n, irp, icol, cursor, keys);
     return hipGetLastError();
 }
 
@@ -251,7 +267,7 @@ __device__ __forceinline__ void emit(int q, u64 key, const R* __restrict__ val, 
 // and gives each key its rank among the keys of its column (a linear count;
 // lanes of one column read the same LDS words, which broadcast).  The rank is
 // the key's final offset in its column, so it is emitted straight away.
-constexpr int kRankCap = 6144;
+constexpr int kRankCap = 3072;
 
 template <typename R>
 __global__ void __launch_bounds__(kBlock)
@@ -260,6 +276,7 @@ k_sort_rank(int n, const int* __restrict__ ccp, const u64* __restrict__ keys, co
     __shared__ int sp[kBlock + 1];
     __shared__ unsigned long long s_long[kBlock / kWave];
     __shared__ u64 sk[kRankCap];
+    __shared__ uint8_t sc[kRankCap];     // column of each staged key, relative to j0
     const int j0 = (int)xcd_block(blockIdx.x, gridDim.x) * kBlock;
     const int cols = min(kBlock, n - j0);
     const int t = threadIdx.x;
@@ -290,13 +307,18 @@ k_sort_rank(int n, const int* __restrict__ ccp, const u64* __restrict__ keys, co
         const int c1 = lo;
         const int base = sp[c0], span = sp[c1] - base;
         for (int q = t; q < span; q += kBlock) sk[q] = keys[base + q];
+        if (t >= c0 && t < c1)
+            for (int q = sp[t] - base; q < sp[t + 1] - base; ++q) sc[q] = (uint8_t)t;
         __syncthreads();
         for (int q = t; q < span; q += kBlock) {
             const u64 key = sk[q];
-            const int c = last_le(sp, c0, c1 - 1, base + q);
+            const int c = sc[q];
             const int s = sp[c] - base, e = sp[c + 1] - base;
-            int rank = 0;
-            for (int k2 = s; k2 < e; ++k2) rank += sk[k2] < key;
+            int rank = 0, k2 = s;
+            for (; k2 + 4 <= e; k2 += 4)
+                rank += (int)(sk[k2] < key) + (int)(sk[k2 + 1] < key) + (int)(sk[k2 + 2] < key) +
+                        (int)(sk[k2 + 3] < key);
+            for (; k2 < e; ++k2) rank += (int)(sk[k2] < key);
             emit<R>(sp[c] + rank, key, val, irow_t, val_t);
         }
         __syncthreads();
