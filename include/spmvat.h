@@ -216,7 +216,7 @@ spmv_status at_table_build(const double *d, const double *r, const int32_t *feas
 
 /* Host only.  On-line phase of section 2.2.  k_repeats <= 0: the paper's
  * rule, ELL_ROW when D_mat < D* and ELL-Row fits the plan's limit, else
- * CRS (variant 0).  k_repeats > 0 and a calibrated table: the option with
+ * CRS (variant 1, the library's CRS kernel, which D* is measured against).  k_repeats > 0 and a calibrated table: the option with
  * the least estimated transformation + k_repeats SpMVs among CRS (both
  * variants), COO_ROW and ELL_ROW (when it fits); ties keep CRS. */
 spmv_status at_choose_format(const spmv_plan *p, const at_table *t, int64_t k_repeats,

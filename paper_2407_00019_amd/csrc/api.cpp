@@ -474,7 +474,7 @@ SPMV_API spmv_status at_choose_format_stats(const spmv_stats* st, spmv_dtype dt,
         // the paper's on-line phase: ELL when D_mat < D*
         d.rule = 0;
         if (d.feasible_ell && st->d_mat < t->d_star) { *fmt = SPMV_ELL_ROW; *variant = 0; }
-        else { *fmt = SPMV_CRS; *variant = 0; }
+        else { *fmt = SPMV_CRS; *variant = 1; }
     } else {
         // least estimated transformation + k SpMVs; ties keep CRS
         d.rule = 1;

@@ -1,0 +1,238 @@
+"""Off-line phase of the auto-tuner (section 2.2), run once per machine.
+
+For each benchmark matrix (the row-length sweep: n = 1,048,576, mean 32
+entries per row, D_mat = 0, 0.125, ..., 4) it measures on the GPU the CRS
+SpMV time t_crs, the ELL-Row SpMV time t_ell and the CRS -> ELL-Row
+transformation time t_trans, and computes SP = t_crs / t_ell (Eq. (1)),
+TT = t_trans / t_crs (Eq. (2), as the transformation cost in CRS-SpMV units),
+R_ell = SP / TT (Eq. (3)) and D_mat (Eq. (4)).  D* is then the smallest D_mat
+whose R_ell falls below c = 1 (at_table_build); points where ELL does not
+fit the memory limit are recorded as infeasible and left out, as the paper
+did for torso1.  The same timings calibrate the cost model used by the
+amortised (k-aware) decision: algorithmic bytes per second of each format,
+variant and transformation per D_mat bucket.
+
+    python -m paper_2407_00019_amd.offline [--points 0,4,8] [--out FILE]
+
+Writes at_table.json next to this file by default and prints one JSON line
+per point.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+import torch
+
+import paper_2407_00019_amd as spmvat
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(_HERE)
+
+
+def _bytes(fmt, n, nnz, width, vb, xb):
+    if fmt == "crs":
+        return (vb + 4) * nnz + 4 * (n + 1) + 2 * xb * n
+    if fmt == "coo_row":
+        return (vb + 8) * nnz + 2 * xb * n
+    if fmt == "ell_row":
+        return (vb + 4) * n * width + 2 * xb * n
+    raise ValueError(fmt)
+
+
+def _trans_bytes(fmt, n, nnz, width, vb):
+    if fmt == "coo_row":
+        return 4 * (n + 1) + 4 * nnz
+    if fmt == "ell_row":
+        return (vb + 4) * nnz + 4 * (n + 1) + (vb + 4) * n * width
+    raise ValueError(fmt)
+
+
+def time_call(fn, reps=7, warm=2):
+    """Median of reps event-timed calls on torch's current stream (ms)."""
+    for _ in range(warm):
+        fn()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return statistics.median(ts)
+
+
+def measure_point(m, dtype, x, reps=7):
+    """Timings of one matrix in one value type.  Returns a dict (ms)."""
+    dev = torch.device("cuda:0")
+    irp = torch.from_numpy(m.irp).to(dev)
+    icol = torch.from_numpy(m.icol).to(dev)
+    val = torch.from_numpy(m.val).to(dev)
+    if dtype != spmvat.F64:
+        val = spmvat.convert_values(val, dtype)
+    xd = x.to(dev) if dtype == spmvat.F64 else x.to(dev).float()
+    plan = spmvat.Plan(irp, icol, val)
+    st = plan.stats
+    n, nnz = m.n, m.nnz
+    vb, xb = val.element_size(), xd.element_size()
+    y = torch.empty_like(xd)
+    out = {"n": n, "nnz": nnz, "d_mat": st.d_mat, "width": st.max_row, "dtype": dtype}
+    out["t_crs_scalar"] = time_call(lambda: plan.spmv(spmvat.CRS, xd, y, 0), reps)
+    out["t_crs_best"] = time_call(lambda: plan.spmv(spmvat.CRS, xd, y, 1), reps)
+    coo_buf = plan._alloc(spmvat.COO_ROW)[0]
+    out["t_trans_coo"] = time_call(lambda: spmvat.csr_to_coo(plan.handle, 0, coo_buf), reps)
+    out["t_coo"] = time_call(lambda: plan.spmv(spmvat.COO_ROW, xd, y, 0), reps)
+    s, sz = plan.sizes(spmvat.ELL_ROW)
+    out["ell_feasible"] = s == spmvat.SPMV_OK
+    y_crs = plan.spmv(spmvat.CRS, xd, None, 1)
+    if out["ell_feasible"]:
+        ell_buf = plan._alloc(spmvat.ELL_ROW)[0]
+        out["t_trans_ell"] = time_call(lambda: spmvat.csr_to_ell(plan.handle, 0, ell_buf), reps)
+        out["t_ell"] = time_call(lambda: plan.spmv(spmvat.ELL_ROW, xd, y, 0), reps)
+        del ell_buf
+    torch.cuda.synchronize()
+    out["y"] = y_crs.double().cpu().numpy()
+    out["bytes"] = {"crs": _bytes("crs", n, nnz, st.max_row, vb, xb), "coo_row": _bytes("coo_row", n, nnz, 0, vb, xb),
+                    "ell_row": _bytes("ell_row", n, nnz, st.max_row, vb, xb),
+                    "trans_coo": _trans_bytes("coo_row", n, nnz, 0, vb),
+                    "trans_ell": _trans_bytes("ell_row", n, nnz, st.max_row, vb)}
+    plan.close()
+    return out
+
+
+def derive(p):
+    """Eqs. (1)-(3) against both CRS kernels."""
+    r = {}
+    for base in ("scalar", "best"):
+        t_crs = p[f"t_crs_{base}"]
+        if p["ell_feasible"]:
+            sp = t_crs / p["t_ell"]
+            tt = p["t_trans_ell"] / t_crs
+            r[f"sp_{base}"], r[f"tt_{base}"], r[f"r_ell_{base}"] = sp, tt, sp / tt
+        else:
+            r[f"sp_{base}"] = r[f"tt_{base}"] = r[f"r_ell_{base}"] = None
+    return r
+
+
+def launch_overhead_s():
+    """Time of a CRS SpMV on a tiny matrix: the fixed cost of one launch."""
+    import gen
+    m = gen.laplace_64x64()
+    dev = torch.device("cuda:0")
+    plan = spmvat.Plan(torch.from_numpy(m.irp).to(dev), torch.from_numpy(m.icol).to(dev),
+                       torch.from_numpy(m.val).to(dev))
+    x = torch.ones(m.n, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    t = time_call(lambda: plan.spmv(spmvat.CRS, x, y, 1), 21, 5)
+    plan.close()
+    return t * 1e-3
+
+
+def bucket(d):
+    return min(spmvat.AT_DBUCKETS - 1, max(0, int(math.floor(d / 0.5))))
+
+
+def main(argv=None):
+    import gen
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--points", default="all", help="comma-separated sweep indices (0..32) or 'all'")
+    ap.add_argument("--dtypes", default="f64,f32,bf16,f16")
+    ap.add_argument("--reps", type=int, default=7)
+    ap.add_argument("--out", default=os.path.join(_HERE, "at_table.json"))
+    ap.add_argument("--c", type=float, default=1.0)
+    a = ap.parse_args(argv)
+    idx = list(range(len(gen.DSWEEP_TARGETS))) if a.points == "all" else [int(s) for s in a.points.split(",")]
+    dts = {"f64": spmvat.F64, "f32": spmvat.F32, "bf16": spmvat.BF16, "f16": spmvat.F16}
+    dlist = [dts[s] for s in a.dtypes.split(",")]
+    launch_s = launch_overhead_s()
+    points = []
+    for i in idx:
+        t0 = time.time()
+        m = gen.dsweep_matrix(i)
+        x = torch.from_numpy(gen.x_uniform(m.n, gen.seed_for(5, 100 + i)))
+        res = {}
+        for dt in dlist:
+            p = measure_point(m, dt, x, a.reps)
+            p.update(derive(p))
+            res[dt] = p
+        y64 = res[spmvat.F64]["y"] if spmvat.F64 in res else None
+        rec = {"index": i, "d_target": gen.DSWEEP_TARGETS[i], "gen_s": round(time.time() - t0, 2)}
+        for dt, p in res.items():
+            name = [k for k, v in dts.items() if v == dt][0]
+            q = {k: v for k, v in p.items() if k not in ("y",)}
+            if y64 is not None and dt != spmvat.F64:
+                q["rel_l2_vs_f64"] = float(np.linalg.norm(p["y"] - y64) / np.linalg.norm(y64))
+            rec[name] = q
+        points.append(rec)
+        print(json.dumps({k: (v if not isinstance(v, dict) else {kk: vv for kk, vv in v.items() if kk != "bytes"})
+                          for k, v in rec.items()}), flush=True)
+
+    # the D_mat - R_ell graph in binary64 and D*, against both CRS kernels
+    f64 = [p["f64"] for p in points if "f64" in p]
+    table = {"c": a.c, "machine": torch.cuda.get_device_name(0), "points": len(f64)}
+    for base in ("scalar", "best"):
+        d = [q["d_mat"] for q in f64]
+        r = [q[f"r_ell_{base}"] if q["ell_feasible"] else 0.0 for q in f64]
+        feas = [1 if q["ell_feasible"] else 0 for q in f64]
+        t = spmvat.at_table_build(d, r, feas, a.c)
+        table[f"d_star_vs_{base}"] = t.d_star if math.isfinite(t.d_star) else "inf"
+        table[f"graph_vs_{base}"] = [[dd, rr, ff] for dd, rr, ff in zip(d, r, feas)]
+    # the on-line paper rule falls back to the library's best CRS kernel, so
+    # D* is taken against it
+    table["d"] = [q["d_mat"] for q in f64]
+    table["r"] = [q["r_ell_best"] if q["ell_feasible"] else 0.0 for q in f64]
+    table["feasible"] = [1 if q["ell_feasible"] else 0 for q in f64]
+    # cost model: mean algorithmic bytes/s per format, variant and D bucket
+    spmv_bps = {str(spmvat.CRS): [[0.0] * spmvat.AT_DBUCKETS, [0.0] * spmvat.AT_DBUCKETS],
+                str(spmvat.COO_ROW): [[0.0] * spmvat.AT_DBUCKETS, [0.0] * spmvat.AT_DBUCKETS],
+                str(spmvat.ELL_ROW): [[0.0] * spmvat.AT_DBUCKETS, [0.0] * spmvat.AT_DBUCKETS]}
+    trans_bps = {str(spmvat.COO_ROW): [0.0] * spmvat.AT_DBUCKETS, str(spmvat.ELL_ROW): [0.0] * spmvat.AT_DBUCKETS}
+    acc = {}
+    for q in f64:
+        b = bucket(q["d_mat"])
+        B = q["bytes"]
+        obs = [((spmvat.CRS, 0), B["crs"] / (q["t_crs_scalar"] * 1e-3 - launch_s)),
+               ((spmvat.CRS, 1), B["crs"] / (q["t_crs_best"] * 1e-3 - launch_s)),
+               ((spmvat.COO_ROW, 0), B["coo_row"] / (q["t_coo"] * 1e-3 - 2 * launch_s)),
+               (("t", spmvat.COO_ROW), B["trans_coo"] / (q["t_trans_coo"] * 1e-3 - launch_s))]
+        if q["ell_feasible"]:
+            obs += [((spmvat.ELL_ROW, 0), B["ell_row"] / (q["t_ell"] * 1e-3 - launch_s)),
+                    (("t", spmvat.ELL_ROW), B["trans_ell"] / (q["t_trans_ell"] * 1e-3 - launch_s))]
+        for key, v in obs:
+            acc.setdefault((key, b), []).append(max(v, 1.0))
+    for (key, b), vals in acc.items():
+        v = statistics.mean(vals)
+        if key[0] == "t":
+            trans_bps[str(key[1])][b] = v
+        else:
+            spmv_bps[str(key[0])][key[1]][b] = v
+    # buckets without a sample take the nearest sampled bucket below (or above)
+    def fill(arr):
+        for k in range(len(arr)):
+            if arr[k] == 0.0:
+                lower = [arr[j] for j in range(k - 1, -1, -1) if arr[j] > 0]
+                upper = [arr[j] for j in range(k + 1, len(arr)) if arr[j] > 0]
+                arr[k] = lower[0] if lower else (upper[0] if upper else 0.0)
+    for f in spmv_bps.values():
+        for v in f:
+            fill(v)
+    for v in trans_bps.values():
+        fill(v)
+    table["cost_model"] = {"spmv_bps": spmv_bps, "trans_bps": trans_bps, "launch_s": launch_s}
+    table["sweep"] = points
+    with open(a.out, "w") as f:
+        json.dump(table, f, indent=1, default=float)
+    print(json.dumps({"d_star_vs_scalar": table["d_star_vs_scalar"], "d_star_vs_best": table["d_star_vs_best"],
+                      "launch_us": launch_s * 1e6, "out": a.out}), flush=True)
+
+
+if __name__ == "__main__":
+    sys.path.insert(0, ROOT)
+    main()
