@@ -241,6 +241,84 @@ void spmv_plan_destroy(spmv_plan *p);
 const char *spmv_status_string(spmv_status s);
 const char *spmv_plan_last_error(const spmv_plan *p);
 
+/* -------------------------------------------------------------- serving
+ *
+ * A continuous-batching SpMV server built on the calls above: the on-line
+ * auto-tuning of section 2.2 applied per request, with the transformation
+ * amortised over the request's declared number of SpMVs (the discussion of
+ * iteration counts after the on-line phase).  Binary32 values, x and y.
+ *
+ * Jobs become visible at their arrival time and wait in FIFO order.  A job
+ * is admitted when one of `slots` HIP streams is free and its CRS footprint
+ * fits in the server's device arena (one allocation of hbm_cap bytes made
+ * at creation).  Its statistics are computed and read back asynchronously;
+ * then the format is chosen (policy 0: at_choose_format_stats with k = the
+ * job's k; policy 1: CRS variant 1), allocated only if it fits right now
+ * (else the job stays in CRS), built, and the chain
+ *     y_1 = A x_0,  x_t = 2^-shift y_t,  y_{t+1} = A x_t   (t < k)
+ * runs on the slot's stream; y_k is copied to y_out.  Jobs on different
+ * slots overlap on the device.  Host arrays must stay valid until the job is
+ * reported; pinned host memory lets the copies run asynchronously. */
+
+typedef struct spmv_server spmv_server;
+
+typedef struct {
+    int32_t slots;       /* jobs in flight at once, one HIP stream each, 1..64 */
+    int32_t policy;      /* 0: per-job k-aware choice, 1: always CRS (variant 1) */
+    size_t hbm_cap;      /* device bytes the server owns */
+    at_table table;      /* auto-tuning table for policy 0 */
+} spmv_server_config;
+
+typedef struct {
+    int64_t id;
+    double arrival_s;          /* seconds after spmv_server_start; < 0: at submission */
+    int32_t n;
+    int64_t nnz;
+    const int32_t *irp;        /* host, n+1 */
+    const int32_t *icol;       /* host, nnz */
+    const float *val;          /* host, nnz, binary32 */
+    const float *x0;           /* host, n */
+    int32_t k;                 /* SpMVs in the chain, >= 1 */
+    int32_t shift;             /* 0..126 */
+    float *y_out;              /* host, n: receives y_k */
+} spmv_job;
+
+typedef struct {
+    int64_t id;
+    int32_t status;            /* spmv_status of the job */
+    int32_t format, variant;   /* format used (-1 if never admitted) */
+    double arrival_s, admit_s, ready_s, done_s;   /* seconds after start */
+    double d_mat;
+    size_t device_bytes;       /* arena bytes the job held */
+} spmv_job_result;
+
+/* Creates the server on the current device (allocates hbm_cap bytes and the
+ * slots' streams).  SPMV_E_TOO_LARGE if the allocation fails. */
+spmv_status spmv_server_create(const spmv_server_config *cfg, spmv_server **out);
+/* Starts the scheduler thread; arrival times count from here. */
+spmv_status spmv_server_start(spmv_server *s);
+/* Queues a job (thread-safe); SPMV_E_ARG for an invalid descriptor.  A job
+ * whose CRS footprint exceeds hbm_cap is reported with SPMV_E_TOO_LARGE. */
+spmv_status spmv_server_submit(spmv_server *s, const spmv_job *job);
+/* Blocks until every submitted job is reported, or SPMV_E_NOT_READY after
+ * timeout_s seconds. */
+spmv_status spmv_server_wait(spmv_server *s, double timeout_s);
+/* Copies up to cap results, in completion order; returns how many. */
+int32_t spmv_server_results(spmv_server *s, spmv_job_result *out, int32_t cap);
+/* Stops the scheduler (jobs in flight are drained) and frees everything. */
+void spmv_server_destroy(spmv_server *s);
+
+/* Host-only offset allocator of the server's arena, exported for callers
+ * that sub-allocate one device block themselves: first fit, 256-byte
+ * granularity, free neighbours coalesce.  Offsets, not pointers. */
+typedef struct spmv_arena spmv_arena;
+spmv_arena *spmv_arena_create(size_t bytes);
+int64_t spmv_arena_alloc(spmv_arena *a, size_t bytes);      /* offset, or -1 when no block fits */
+void spmv_arena_free(spmv_arena *a, int64_t off, size_t bytes);
+size_t spmv_arena_free_bytes(const spmv_arena *a);
+size_t spmv_arena_largest(const spmv_arena *a);
+void spmv_arena_destroy(spmv_arena *a);
+
 #ifdef __cplusplus
 }
 #endif

@@ -63,6 +63,25 @@ class at_table(ctypes.Structure):
                 ("trans_bps", (ctypes.c_double * AT_DBUCKETS) * 6), ("launch_s", ctypes.c_double)]
 
 
+class spmv_server_config(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("policy", ctypes.c_int32), ("hbm_cap", ctypes.c_size_t),
+                ("table", at_table)]
+
+
+class spmv_job(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("arrival_s", ctypes.c_double), ("n", ctypes.c_int32),
+                ("nnz", ctypes.c_int64), ("irp", ctypes.c_void_p), ("icol", ctypes.c_void_p),
+                ("val", ctypes.c_void_p), ("x0", ctypes.c_void_p), ("k", ctypes.c_int32),
+                ("shift", ctypes.c_int32), ("y_out", ctypes.c_void_p)]
+
+
+class spmv_job_result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int32), ("format", ctypes.c_int32),
+                ("variant", ctypes.c_int32), ("arrival_s", ctypes.c_double), ("admit_s", ctypes.c_double),
+                ("ready_s", ctypes.c_double), ("done_s", ctypes.c_double), ("d_mat", ctypes.c_double),
+                ("device_bytes", ctypes.c_size_t)]
+
+
 class at_decision(ctypes.Structure):
     _fields_ = [("rule", ctypes.c_int32), ("feasible_ell", ctypes.c_int32), ("d_mat", ctypes.c_double),
                 ("t_crs_hat", ctypes.c_double), ("t_fmt_hat", ctypes.c_double),
@@ -118,6 +137,30 @@ def lib():
         L.spmv_status_string.restype = ctypes.c_char_p
         L.spmv_plan_last_error.argtypes = [P]
         L.spmv_plan_last_error.restype = ctypes.c_char_p
+        L.spmv_server_create.argtypes = [ctypes.POINTER(spmv_server_config), ctypes.POINTER(P)]
+        L.spmv_server_create.restype = st
+        L.spmv_server_start.argtypes = [P]
+        L.spmv_server_start.restype = st
+        L.spmv_server_submit.argtypes = [P, ctypes.POINTER(spmv_job)]
+        L.spmv_server_submit.restype = st
+        L.spmv_server_wait.argtypes = [P, f64]
+        L.spmv_server_wait.restype = st
+        L.spmv_server_results.argtypes = [P, ctypes.POINTER(spmv_job_result), i32]
+        L.spmv_server_results.restype = i32
+        L.spmv_server_destroy.argtypes = [P]
+        L.spmv_server_destroy.restype = None
+        L.spmv_arena_create.argtypes = [sz]
+        L.spmv_arena_create.restype = P
+        L.spmv_arena_alloc.argtypes = [P, sz]
+        L.spmv_arena_alloc.restype = i64
+        L.spmv_arena_free.argtypes = [P, i64, sz]
+        L.spmv_arena_free.restype = None
+        L.spmv_arena_free_bytes.argtypes = [P]
+        L.spmv_arena_free_bytes.restype = sz
+        L.spmv_arena_largest.argtypes = [P]
+        L.spmv_arena_largest.restype = sz
+        L.spmv_arena_destroy.argtypes = [P]
+        L.spmv_arena_destroy.restype = None
         _LIB = L
     return _LIB
 
@@ -247,6 +290,34 @@ def spmv_convert_values(inp, out, to: int, stream=None) -> None:
 
 def spmv_plan_destroy(plan) -> None:
     lib().spmv_plan_destroy(plan)
+
+
+def spmv_server_create(cfg: spmv_server_config) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().spmv_server_create(ctypes.byref(cfg), ctypes.byref(h)), "spmv_server_create")
+    return h
+
+
+def spmv_server_start(srv) -> None:
+    _check(lib().spmv_server_start(srv), "spmv_server_start")
+
+
+def spmv_server_submit(srv, job: spmv_job) -> None:
+    _check(lib().spmv_server_submit(srv, ctypes.byref(job)), "spmv_server_submit")
+
+
+def spmv_server_wait(srv, timeout_s: float) -> int:
+    return lib().spmv_server_wait(srv, timeout_s)
+
+
+def spmv_server_results(srv, cap: int):
+    out = (spmv_job_result * max(cap, 1))()
+    m = lib().spmv_server_results(srv, out, cap)
+    return [out[i] for i in range(m)]
+
+
+def spmv_server_destroy(srv) -> None:
+    lib().spmv_server_destroy(srv)
 
 
 # ---------------------------------------------------------- convenience

@@ -12,31 +12,11 @@
 
 #include "../../include/spmvat.h"
 #include "kernels.h"
+#include "plan_internal.h"
 
 using namespace spmvat;
 
 #define SPMV_API extern "C" __attribute__((visibility("default")))
-
-struct spmv_plan {
-    int32_t n = 0;
-    int64_t nnz = 0;
-    spmv_dtype dt = SPMV_F64;
-    const int32_t* irp = nullptr;
-    const int32_t* icol = nullptr;
-    const void* val = nullptr;
-    char* work = nullptr;
-    size_t work_bytes = 0;
-    spmv_stats st{};
-    size_t limit = 0;
-    // formats built so far (borrowed caller buffers; arrays may be null when nnz = 0)
-    bool has_coo_row = false, has_ccs = false, has_coo_col = false;
-    const int32_t* irow = nullptr;                                            // COO-Row
-    const int32_t* ccp = nullptr; const int32_t* irow_t = nullptr; const void* val_t = nullptr;  // CCS
-    const int32_t* jcol = nullptr;                                            // COO-Col
-    int32_t ell_w = -1; const void* ell_val = nullptr; const int32_t* ell_col = nullptr;        // ELL-Row
-    int32_t ellc_w = -1; const void* ellc_val = nullptr; const int32_t* ellc_row = nullptr;     // ELL-Col
-    std::string err;
-};
 
 namespace {
 
@@ -123,57 +103,71 @@ SPMV_API size_t spmv_plan_workspace_bytes(int32_t n, int64_t nnz) {
     return plan_ws_bytes(nnz < 0 ? 0 : nnz);
 }
 
-SPMV_API spmv_status spmv_plan_create(spmv_plan** plan, int32_t n, int64_t nnz, const int32_t* irp,
-                                      const int32_t* icol, const void* val, spmv_dtype val_type,
-                                      void* plan_work, size_t plan_work_bytes, void* stream) {
-    if (!plan) return SPMV_E_ARG;
-    *plan = nullptr;
+namespace spmvat {
+
+spmv_status plan_begin(spmv_plan* p, int32_t n, int64_t nnz, const int32_t* irp, const int32_t* icol,
+                       const void* val, spmv_dtype val_type, void* plan_work, size_t plan_work_bytes,
+                       RowStats* host_stats, hipStream_t s) {
     if (n < 1 || nnz < 0 || nnz > INT32_MAX || !valid_dtype(val_type)) return SPMV_E_ARG;
     if (!irp || !plan_work || (nnz > 0 && (!icol || !val))) return SPMV_E_ARG;
     if (!aligned16(irp) || !aligned16(icol) || !aligned16(val) || !aligned16(plan_work)) return SPMV_E_ARG;
     if (plan_work_bytes < plan_ws_bytes(nnz)) return SPMV_E_ARG;
-    spmv_plan* p = new (std::nothrow) spmv_plan();
-    if (!p) return SPMV_E_ARG;
     p->n = n; p->nnz = nnz; p->dt = val_type;
     p->irp = irp; p->icol = icol; p->val = val;
     p->work = static_cast<char*>(plan_work); p->work_bytes = plan_work_bytes;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    RowStats rs{};
     hipError_t e = launch_row_stats(n, nnz, irp, icol, plan_partials(p), plan_rowstats(p), s);
-    if (e == hipSuccess) e = hipMemcpyAsync(&rs, plan_rowstats(p), sizeof(rs), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) { delete p; return SPMV_E_HIP; }
-    if (rs.flags != 0) { delete p; return SPMV_E_MATRIX; }
+    if (e == hipSuccess) e = hipMemcpyAsync(host_stats, plan_rowstats(p), sizeof(RowStats), hipMemcpyDeviceToHost, s);
+    return e == hipSuccess ? SPMV_OK : hip_fail(p, e);
+}
+
+spmv_status plan_finish(spmv_plan* p, const RowStats& rs) {
+    if (rs.flags != 0) return SPMV_E_MATRIX;
+    const int32_t n = p->n;
     spmv_stats& st = p->st;
-    st.n = n; st.nnz = nnz;
+    st.n = n; st.nnz = p->nnz;
     st.sum_len = (int64_t)rs.s1; st.sum_len2 = (int64_t)rs.s2;
     st.max_row = rs.max_len; st.min_row = (int32_t)rs.min_len; st.max_col = -1;
     // Eq. (4) from the exact integer moments: num = n*s2 - s1^2 (= n^2 sigma^2),
     // rounded once; sigma = sqrt(num)/n, D_mat = sqrt(num)/s1.
     const unsigned __int128 num = (unsigned __int128)(uint64_t)n * (uint64_t)rs.s2 -
                                   (unsigned __int128)rs.s1 * (unsigned __int128)rs.s1;
-    uint64_t hi = (uint64_t)(num >> 64), lo = (uint64_t)num;
+    const uint64_t hi = (uint64_t)(num >> 64), lo = (uint64_t)num;
     double numd;
-    {
-        // nearest binary64 (ties to even) of the 128-bit integer, written with
-        // 64-bit halves: the top 64 significant bits carry the rounding, the
-        // bits below them only stick
-        if (hi == 0) {
-            numd = (double)lo;  // the hardware conversion rounds to nearest even
-        } else {
-            int lz = __builtin_clzll(hi);
-            int sh = 64 - lz;                         // bits of num beyond the low 64
-            uint64_t top = (hi << lz) | (lz ? (lo >> (64 - lz)) : 0);   // top 64 bits
-            uint64_t rest = lz ? (lo << lz) : lo;                        // bits shifted out
-            top |= (rest != 0) ? 1u : 0u;            // sticky below the 64 kept bits
-            numd = std::ldexp((double)top, sh);      // one rounding of 64 -> 53 bits
-        }
+    if (hi == 0) {
+        numd = (double)lo;   // the conversion rounds to nearest even
+    } else {
+        // nearest binary64 of the 128-bit integer: the top 64 significant bits
+        // carry the rounding, the bits below them only stick
+        const int lz = __builtin_clzll(hi);
+        const int sh = 64 - lz;
+        uint64_t top = (hi << lz) | (lz ? (lo >> (64 - lz)) : 0);
+        const uint64_t rest = lz ? (lo << lz) : lo;
+        top |= (rest != 0) ? 1u : 0u;
+        numd = std::ldexp((double)top, sh);   // one rounding of 64 -> 53 bits
     }
     const double r = std::sqrt(numd);
     st.mu = (double)rs.s1 / (double)n;
     st.sigma = r / (double)n;
     st.d_mat = rs.s1 == 0 ? 0.0 : r / (double)rs.s1;
     p->limit = 8 * crs_bytes(p);
+    return SPMV_OK;
+}
+
+}  // namespace spmvat
+
+SPMV_API spmv_status spmv_plan_create(spmv_plan** plan, int32_t n, int64_t nnz, const int32_t* irp,
+                                      const int32_t* icol, const void* val, spmv_dtype val_type,
+                                      void* plan_work, size_t plan_work_bytes, void* stream) {
+    if (!plan) return SPMV_E_ARG;
+    *plan = nullptr;
+    spmv_plan* p = new (std::nothrow) spmv_plan();
+    if (!p) return SPMV_E_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    RowStats rs{};
+    spmv_status st = plan_begin(p, n, nnz, irp, icol, val, val_type, plan_work, plan_work_bytes, &rs, s);
+    if (st == SPMV_OK && hipStreamSynchronize(s) != hipSuccess) st = SPMV_E_HIP;
+    if (st == SPMV_OK) st = plan_finish(p, rs);
+    if (st != SPMV_OK) { delete p; return st; }
     *plan = p;
     return SPMV_OK;
 }

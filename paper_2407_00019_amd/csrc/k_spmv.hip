@@ -315,11 +315,28 @@ size_t coo_carry_bytes(int64_t nnz) {
     return (size_t)(nb > 0 ? nb : 1) * sizeof(Carry<double>);
 }
 
+// x_{t+1} = 2^-shift y_t for the dependent SpMV chains of the server
+// (a power-of-two scaling: exact unless the result leaves the normal range).
+template <typename X>
+__global__ void __launch_bounds__(kBlock) k_scale_pow2(int n, int shift, const X* __restrict__ in, X* __restrict__ out) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) out[i] = ldexp(in[i], -shift);
+}
+
 // ---------------------------------------------------------- dispatch
 
 __global__ void __launch_bounds__(kBlock) k_fill_zero(uint32_t* p, int64_t words) {
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < words; i += stride) p[i] = 0u;
+}
+
+hipError_t launch_scale_pow2(int dtype, int n, int shift, const void* in, void* out, hipStream_t s) {
+    const unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_scale_pow2<double>, dim3(blocks), dim3(kBlock), 0, s, n, shift, (const double*)in, (double*)out);
+    else
+        hipLaunchKernelGGL(k_scale_pow2<float>, dim3(blocks), dim3(kBlock), 0, s, n, shift, (const float*)in, (float*)out);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_zero(void* y, int64_t bytes, hipStream_t s) {

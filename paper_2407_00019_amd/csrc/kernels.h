@@ -60,6 +60,8 @@ hipError_t launch_ell_pack(int n, int width, const int* ptr, const int* idx, con
 
 // ---- SpMV (dtype: 0 F64, 1 F32, 2 BF16, 3 F16)
 hipError_t launch_fill_zero(void* y, int64_t bytes, hipStream_t s);
+// out = 2^-shift in (dtype 0: binary64, else binary32)
+hipError_t launch_scale_pow2(int dtype, int n, int shift, const void* in, void* out, hipStream_t s);
 hipError_t launch_spmv_crs_scalar(int dtype, int n, const int* irp, const int* icol, const void* val,
                                   const void* x, void* y, hipStream_t s);
 hipError_t launch_spmv_crs_stream(int dtype, int n, const int* irp, const int* icol, const void* val,

@@ -1,0 +1,403 @@
+// Continuous-batching SpMV server: the auto-tuner of section 2.2 applied per
+// request, with the transformation amortised over the request's declared
+// number of SpMVs (the iteration-count discussion after the on-line phase).
+//
+// One scheduler thread owns the device side.  Jobs become visible at their
+// arrival time and wait in FIFO order; a job is admitted when a slot (one
+// HIP stream) is free and its CRS footprint fits in the device arena.  An
+// admitted job moves through:
+//   INGEST  host-to-device copies, row statistics, statistics read back
+//           through pinned memory -- all asynchronous, finished by an event;
+//   RUN     format choice from D_mat, the row lengths and k (the transformed
+//           format is allocated only if it fits now, else the job stays in
+//           CRS), the optional transformation, the chain of k SpMVs
+//           x_{t+1} = 2^-shift y_t, and the copy of y_k back to the host.
+// The loop never blocks on one job: it polls events, so work from different
+// jobs overlaps on the device and new jobs are admitted as slots and memory
+// free up.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "../../include/spmvat.h"
+#include "kernels.h"
+#include "plan_internal.h"
+
+#define SPMV_API extern "C" __attribute__((visibility("default")))
+
+using namespace spmvat;
+
+// ------------------------------------------------------------- arena
+
+struct spmv_arena {
+    // free blocks: offset -> size, kept coalesced
+    std::map<size_t, size_t> free_;
+    size_t cap = 0;
+    size_t free_bytes = 0;
+    static constexpr size_t kGrain = 256;
+
+    explicit spmv_arena(size_t bytes) : cap(bytes / kGrain * kGrain), free_bytes(cap) {
+        if (cap) free_[0] = cap;
+    }
+    static size_t round(size_t b) { return (std::max<size_t>(b, 1) + kGrain - 1) / kGrain * kGrain; }
+    int64_t alloc(size_t bytes) {
+        const size_t need = round(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= need) {
+                const size_t off = it->first, sz = it->second;
+                free_.erase(it);
+                if (sz > need) free_[off + need] = sz - need;
+                free_bytes -= need;
+                return (int64_t)off;
+            }
+        }
+        return -1;
+    }
+    void release(int64_t off, size_t bytes) {
+        size_t o = (size_t)off, sz = round(bytes);
+        free_bytes += sz;
+        auto next = free_.lower_bound(o);
+        if (next != free_.end() && o + sz == next->first) {
+            sz += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == o) {
+                prev->second += sz;
+                return;
+            }
+        }
+        free_[o] = sz;
+    }
+    size_t largest() const {
+        size_t m = 0;
+        for (auto& kv : free_) m = std::max(m, kv.second);
+        return m;
+    }
+};
+
+SPMV_API spmv_arena* spmv_arena_create(size_t bytes) { return new (std::nothrow) spmv_arena(bytes); }
+SPMV_API int64_t spmv_arena_alloc(spmv_arena* a, size_t bytes) { return a ? a->alloc(bytes) : -1; }
+SPMV_API void spmv_arena_free(spmv_arena* a, int64_t off, size_t bytes) {
+    if (a && off >= 0) a->release(off, bytes);
+}
+SPMV_API size_t spmv_arena_free_bytes(const spmv_arena* a) { return a ? a->free_bytes : 0; }
+SPMV_API size_t spmv_arena_largest(const spmv_arena* a) { return a ? a->largest() : 0; }
+SPMV_API void spmv_arena_destroy(spmv_arena* a) { delete a; }
+
+// ------------------------------------------------------------- server
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+enum class SlotState { kFree, kIngest, kRun };
+
+struct Block {
+    int64_t off = -1;
+    size_t bytes = 0;
+};
+
+struct Slot {
+    SlotState state = SlotState::kFree;
+    hipStream_t stream = nullptr;
+    hipEvent_t event = nullptr;
+    RowStats* host_stats = nullptr;   // pinned
+    spmv_job job{};
+    spmv_job_result res{};
+    spmv_plan plan;
+    Block crs, fmt;
+    char* dev = nullptr;              // start of the CRS block
+    int32_t *irp = nullptr, *icol = nullptr;
+    float *val = nullptr, *x = nullptr, *y = nullptr;
+    void* pwork = nullptr;
+    size_t pwork_bytes = 0;
+};
+
+inline size_t r256(size_t b) { return (std::max<size_t>(b, 1) + 255) / 256 * 256; }
+
+// Device bytes of a job in CRS: the arrays, x, y and the plan workspace.
+size_t crs_footprint(const spmv_job& j) {
+    return r256(4 * ((size_t)j.n + 1)) + 2 * r256(4 * (size_t)j.nnz) + 2 * r256(4 * (size_t)j.n) +
+           r256(spmv_plan_workspace_bytes(j.n, j.nnz));
+}
+
+}  // namespace
+
+struct spmv_server {
+    spmv_server_config cfg{};
+    int device = 0;
+    char* base = nullptr;
+    spmv_arena arena{0};
+    std::vector<Slot> slots;
+    std::thread thread;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<spmv_job> pending;     // submitted, sorted by arrival
+    std::deque<spmv_job> ready;       // arrived, FIFO
+    std::vector<spmv_job_result> done;
+    int64_t submitted = 0, completed = 0;
+    std::atomic<bool> stop{false};
+    bool started = false;
+    Clock::time_point t0;
+
+    double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+
+    void finish(Slot& s, int32_t status) {
+        if (s.fmt.off >= 0) arena.release(s.fmt.off, s.fmt.bytes);
+        if (s.crs.off >= 0) arena.release(s.crs.off, s.crs.bytes);
+        s.fmt = Block{};
+        s.crs = Block{};
+        s.res.status = status;
+        s.res.done_s = now();
+        s.state = SlotState::kFree;
+        std::lock_guard<std::mutex> g(mu);
+        done.push_back(s.res);
+        ++completed;
+        cv.notify_all();
+    }
+
+    void fail_unadmitted(const spmv_job& j, int32_t status) {
+        spmv_job_result r{};
+        r.id = j.id;
+        r.status = status;
+        r.arrival_s = j.arrival_s;
+        r.admit_s = r.ready_s = r.done_s = now();
+        r.format = -1;
+        std::lock_guard<std::mutex> g(mu);
+        done.push_back(r);
+        ++completed;
+        cv.notify_all();
+    }
+
+    // Copies in, enqueues the statistics.  False if the arena is full now.
+    bool admit(Slot& s, const spmv_job& j) {
+        const size_t need = crs_footprint(j);
+        const int64_t off = arena.alloc(need);
+        if (off < 0) return false;
+        s.job = j;
+        s.res = spmv_job_result{};
+        s.res.id = j.id;
+        s.res.arrival_s = j.arrival_s;
+        s.res.admit_s = now();
+        s.res.format = -1;
+        s.crs = Block{off, need};
+        s.res.device_bytes = need;
+        char* p = base + off;
+        s.irp = reinterpret_cast<int32_t*>(p); p += r256(4 * ((size_t)j.n + 1));
+        s.icol = reinterpret_cast<int32_t*>(p); p += r256(4 * (size_t)j.nnz);
+        s.val = reinterpret_cast<float*>(p); p += r256(4 * (size_t)j.nnz);
+        s.x = reinterpret_cast<float*>(p); p += r256(4 * (size_t)j.n);
+        s.y = reinterpret_cast<float*>(p); p += r256(4 * (size_t)j.n);
+        s.pwork = p;
+        s.pwork_bytes = spmv_plan_workspace_bytes(j.n, j.nnz);
+        hipError_t e = hipMemcpyAsync(s.irp, j.irp, 4 * ((size_t)j.n + 1), hipMemcpyHostToDevice, s.stream);
+        if (e == hipSuccess && j.nnz > 0)
+            e = hipMemcpyAsync(s.icol, j.icol, 4 * (size_t)j.nnz, hipMemcpyHostToDevice, s.stream);
+        if (e == hipSuccess && j.nnz > 0)
+            e = hipMemcpyAsync(s.val, j.val, 4 * (size_t)j.nnz, hipMemcpyHostToDevice, s.stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(s.x, j.x0, 4 * (size_t)j.n, hipMemcpyHostToDevice, s.stream);
+        s.plan = spmv_plan();
+        spmv_status st = e == hipSuccess ? plan_begin(&s.plan, j.n, j.nnz, s.irp, s.icol, s.val, SPMV_F32, s.pwork,
+                                                      s.pwork_bytes, s.host_stats, s.stream)
+                                         : SPMV_E_HIP;
+        if (st == SPMV_OK && hipEventRecord(s.event, s.stream) != hipSuccess) st = SPMV_E_HIP;
+        if (st != SPMV_OK) {
+            (void)hipStreamSynchronize(s.stream);
+            finish(s, st);
+            return true;
+        }
+        s.state = SlotState::kIngest;
+        return true;
+    }
+
+    // Statistics are back: choose the format, enqueue transformation + chain.
+    void launch_run(Slot& s) {
+        spmv_status st = plan_finish(&s.plan, *s.host_stats);
+        if (st != SPMV_OK) { finish(s, st); return; }
+        s.res.ready_s = now();
+        s.res.d_mat = s.plan.st.d_mat;
+        spmv_format f = SPMV_CRS;
+        int v = 1;
+        if (cfg.policy == 0) {
+            at_decision why{};
+            const size_t limit = std::min(s.plan.limit, arena.largest());
+            if (at_choose_format_stats(&s.plan.st, SPMV_F32, limit, &cfg.table, s.job.k, &f, &v, &why) != SPMV_OK) {
+                f = SPMV_CRS;
+                v = 1;
+            }
+        }
+        if (f != SPMV_CRS) {
+            spmv_sizes sz{};
+            if (spmv_buffer_sizes(&s.plan, f, &sz) != SPMV_OK) {
+                f = SPMV_CRS;
+                v = 1;
+            } else {
+                const size_t need = r256(sz.bytes[0]) + r256(sz.bytes[1]);
+                const int64_t off = arena.alloc(need);
+                if (off < 0) {
+                    f = SPMV_CRS;   // not enough memory now: stay in CRS
+                    v = 1;
+                } else {
+                    s.fmt = Block{off, need};
+                    s.res.device_bytes += need;
+                    spmv_buffers b{};
+                    b.ptr[0] = base + off;
+                    b.bytes[0] = sz.bytes[0];
+                    b.ptr[1] = base + off + r256(sz.bytes[0]);
+                    b.bytes[1] = sz.bytes[1];
+                    st = f == SPMV_ELL_ROW ? csr_to_ell(&s.plan, 0, &b, nullptr, 0, s.stream)
+                                           : csr_to_coo(&s.plan, 0, &b, nullptr, 0, s.stream);
+                    if (st != SPMV_OK) { (void)hipStreamSynchronize(s.stream); finish(s, st); return; }
+                }
+            }
+        }
+        s.res.format = (int32_t)f;
+        s.res.variant = v;
+        for (int32_t t = 0; t < s.job.k; ++t) {
+            st = spmv_exec(&s.plan, f, v, s.x, s.y, s.stream);
+            if (st == SPMV_OK && t + 1 < s.job.k &&
+                launch_scale_pow2(1, s.job.n, s.job.shift, s.y, s.x, s.stream) != hipSuccess)
+                st = SPMV_E_HIP;
+            if (st != SPMV_OK) { (void)hipStreamSynchronize(s.stream); finish(s, st); return; }
+        }
+        hipError_t e = hipMemcpyAsync(s.job.y_out, s.y, 4 * (size_t)s.job.n, hipMemcpyDeviceToHost, s.stream);
+        if (e == hipSuccess) e = hipEventRecord(s.event, s.stream);
+        if (e != hipSuccess) { (void)hipStreamSynchronize(s.stream); finish(s, SPMV_E_HIP); return; }
+        s.state = SlotState::kRun;
+    }
+
+    void loop() {
+        (void)hipSetDevice(device);
+        while (!stop.load(std::memory_order_relaxed)) {
+            bool busy = false;
+            const double t = now();
+            {
+                std::lock_guard<std::mutex> g(mu);
+                while (!pending.empty() && pending.front().arrival_s <= t) {
+                    ready.push_back(pending.front());
+                    pending.pop_front();
+                }
+            }
+            for (Slot& s : slots) {
+                if (s.state == SlotState::kFree) continue;
+                busy = true;
+                const hipError_t q = hipEventQuery(s.event);
+                if (q == hipErrorNotReady) continue;
+                if (q != hipSuccess) { finish(s, SPMV_E_HIP); continue; }
+                if (s.state == SlotState::kIngest) launch_run(s);
+                else finish(s, SPMV_OK);
+            }
+            // admission, in arrival order: a job waits until a slot and its memory are free
+            for (;;) {
+                spmv_job j;
+                {
+                    std::lock_guard<std::mutex> g(mu);
+                    if (ready.empty()) break;
+                    j = ready.front();
+                }
+                if (crs_footprint(j) > arena.cap) {
+                    { std::lock_guard<std::mutex> g(mu); ready.pop_front(); }
+                    fail_unadmitted(j, SPMV_E_TOO_LARGE);
+                    continue;
+                }
+                Slot* free_slot = nullptr;
+                for (Slot& s : slots)
+                    if (s.state == SlotState::kFree) { free_slot = &s; break; }
+                if (!free_slot || !admit(*free_slot, j)) break;
+                { std::lock_guard<std::mutex> g(mu); ready.pop_front(); }
+                busy = true;
+            }
+            if (busy) std::this_thread::yield();
+            else std::this_thread::sleep_for(std::chrono::microseconds(20));
+        }
+    }
+};
+
+SPMV_API spmv_status spmv_server_create(const spmv_server_config* cfg, spmv_server** out) {
+    if (!cfg || !out || cfg->slots < 1 || cfg->slots > 64 || cfg->hbm_cap < 4096 || cfg->policy < 0 ||
+        cfg->policy > 1)
+        return SPMV_E_ARG;
+    *out = nullptr;
+    spmv_server* s = new (std::nothrow) spmv_server();
+    if (!s) return SPMV_E_ARG;
+    s->cfg = *cfg;
+    if (hipGetDevice(&s->device) != hipSuccess) { delete s; return SPMV_E_HIP; }
+    if (hipMalloc(&s->base, cfg->hbm_cap) != hipSuccess) { delete s; return SPMV_E_TOO_LARGE; }
+    s->arena.~spmv_arena();
+    new (&s->arena) spmv_arena(cfg->hbm_cap);
+    s->slots.resize((size_t)cfg->slots);
+    for (Slot& sl : s->slots) {
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.event, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void**>(&sl.host_stats), sizeof(RowStats), hipHostMallocDefault) != hipSuccess) {
+            spmv_server_destroy(s);
+            return SPMV_E_HIP;
+        }
+    }
+    *out = s;
+    return SPMV_OK;
+}
+
+SPMV_API spmv_status spmv_server_start(spmv_server* s) {
+    if (!s || s->started) return SPMV_E_ARG;
+    s->t0 = Clock::now();
+    s->started = true;
+    s->thread = std::thread([s] { s->loop(); });
+    return SPMV_OK;
+}
+
+SPMV_API spmv_status spmv_server_submit(spmv_server* s, const spmv_job* job) {
+    if (!s || !job || job->n < 1 || job->nnz < 0 || job->nnz > INT32_MAX || job->k < 1 || job->shift < 0 ||
+        job->shift > 126 || !job->irp || !job->x0 || !job->y_out || (job->nnz > 0 && (!job->icol || !job->val)))
+        return SPMV_E_ARG;
+    spmv_job j = *job;
+    std::lock_guard<std::mutex> g(s->mu);
+    if (j.arrival_s < 0) j.arrival_s = s->started ? s->now() : 0.0;
+    // keep pending sorted by arrival (submissions normally come in order)
+    auto it = s->pending.end();
+    while (it != s->pending.begin() && std::prev(it)->arrival_s > j.arrival_s) --it;
+    s->pending.insert(it, j);
+    ++s->submitted;
+    return SPMV_OK;
+}
+
+SPMV_API spmv_status spmv_server_wait(spmv_server* s, double timeout_s) {
+    if (!s || !s->started) return SPMV_E_ARG;
+    std::unique_lock<std::mutex> lk(s->mu);
+    const bool ok = s->cv.wait_for(lk, std::chrono::duration<double>(timeout_s),
+                                   [s] { return s->completed == s->submitted; });
+    return ok ? SPMV_OK : SPMV_E_NOT_READY;
+}
+
+SPMV_API int32_t spmv_server_results(spmv_server* s, spmv_job_result* out, int32_t cap) {
+    if (!s || !out || cap <= 0) return 0;
+    std::lock_guard<std::mutex> g(s->mu);
+    const int32_t m = (int32_t)std::min<size_t>((size_t)cap, s->done.size());
+    std::memcpy(out, s->done.data(), sizeof(spmv_job_result) * (size_t)m);
+    return m;
+}
+
+SPMV_API void spmv_server_destroy(spmv_server* s) {
+    if (!s) return;
+    s->stop.store(true);
+    if (s->thread.joinable()) s->thread.join();
+    for (Slot& sl : s->slots) {
+        if (sl.stream) { (void)hipStreamSynchronize(sl.stream); (void)hipStreamDestroy(sl.stream); }
+        if (sl.event) (void)hipEventDestroy(sl.event);
+        if (sl.host_stats) (void)hipHostFree(sl.host_stats);
+    }
+    if (s->base) (void)hipFree(s->base);
+    delete s;
+}

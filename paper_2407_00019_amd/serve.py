@@ -1,0 +1,196 @@
+"""Driver of the continuous-batching SpMV server (spmv_server_* in the C ABI).
+
+Builds a stream of SpMV jobs in pinned host memory, replays one arrival trace
+through the server under a policy (0: per-job k-aware auto-tuning, 1: always
+CRS), and reports jobs/s and latency percentiles.  A job is a dependent chain
+of k SpMVs, y_1 = A x_0 and y_{t+1} = A (2^-shift y_t), the use an iterative
+solver makes of a matrix.
+
+    python -m paper_2407_00019_amd.serve [--jobs 2048] [--rate auto] [--slots 8]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+import paper_2407_00019_amd as spmvat
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@dataclass
+class HostJob:
+    """One request: CRS with binary32 values, x0, the chain length k and the
+    power-of-two scale of the chain, in pinned host memory."""
+    id: int
+    n: int
+    nnz: int
+    irp: torch.Tensor
+    icol: torch.Tensor
+    val: torch.Tensor
+    x0: torch.Tensor
+    y: torch.Tensor
+    k: int
+    shift: int
+    arrival_s: float
+    kind: str = ""
+
+    def descriptor(self, arrival_s: float | None = None) -> spmvat.spmv_job:
+        d = spmvat.spmv_job()
+        d.id = self.id
+        d.arrival_s = self.arrival_s if arrival_s is None else arrival_s
+        d.n, d.nnz = self.n, self.nnz
+        d.irp, d.icol, d.val = self.irp.data_ptr(), self.icol.data_ptr() if self.nnz else None, \
+            self.val.data_ptr() if self.nnz else None
+        d.x0, d.y_out = self.x0.data_ptr(), self.y.data_ptr()
+        d.k, d.shift = self.k, self.shift
+        return d
+
+
+def chain_shift(n, irp, val32) -> int:
+    """Smallest e >= 0 with max_i sum_j |a_ij| <= 2^e, so that the scaled
+    chain cannot grow."""
+    rows = np.repeat(np.arange(n), np.diff(irp))
+    s = np.bincount(rows, weights=np.abs(val32.astype(np.float64)), minlength=n)
+    m = float(s.max()) if n else 0.0
+    return max(0, int(math.ceil(math.log2(m)))) if m > 1.0 else 0
+
+
+def pinned(a: np.ndarray) -> torch.Tensor:
+    t = torch.empty(a.shape[0], dtype=torch.from_numpy(a[:0]).dtype, pin_memory=True)
+    t.numpy()[:] = a
+    return t
+
+
+def build_jobs(specs, seed_x: int = 7) -> list:
+    import gen
+    jobs = []
+    for sp in specs:
+        m = sp.matrix()
+        v32 = m.val.astype(np.float32)
+        x0 = gen.x_uniform(m.n, gen.seed_for(4, 10000 + sp.index)).astype(np.float32)
+        jobs.append(HostJob(sp.index, m.n, m.nnz, pinned(m.irp), pinned(m.icol), pinned(v32), pinned(x0),
+                            torch.empty(m.n, dtype=torch.float32, pin_memory=True), sp.k,
+                            chain_shift(m.n, m.irp, v32), sp.arrival_s, sp.kind))
+    return jobs
+
+
+def load_table() -> spmvat.at_table:
+    path = os.path.join(_HERE, "at_table.json")
+    if not os.path.exists(path):
+        return spmvat.at_table_build([], [], None, 1.0)
+    with open(path) as f:
+        d = json.load(f)
+    t = spmvat.at_table_build(d["d"], d["r"], d["feasible"], d.get("c", 1.0))
+    cm = d.get("cost_model")
+    if cm:
+        t.calibrated = 1
+        for f_, per_v in cm["spmv_bps"].items():
+            for v_, buckets in enumerate(per_v):
+                for b_, val in enumerate(buckets):
+                    t.spmv_bps[int(f_)][v_][b_] = val
+        for f_, buckets in cm["trans_bps"].items():
+            for b_, val in enumerate(buckets):
+                t.trans_bps[int(f_)][b_] = val
+        t.launch_s = cm.get("launch_s", 0.0)
+    return t
+
+
+def run(jobs, policy: int, slots: int = 8, hbm_cap: int = 200 << 30, table=None, arrivals=None,
+        timeout_s: float = 600.0):
+    """Replays the jobs through a fresh server; returns (results, wall_s)."""
+    cfg = spmvat.spmv_server_config()
+    cfg.slots, cfg.policy, cfg.hbm_cap = slots, policy, hbm_cap
+    cfg.table = table if table is not None else load_table()
+    srv = spmvat.spmv_server_create(cfg)
+    try:
+        descs = [j.descriptor(None if arrivals is None else arrivals[i]) for i, j in enumerate(jobs)]
+        for d in descs:
+            spmvat.spmv_server_submit(srv, d)
+        t0 = time.perf_counter()
+        spmvat.spmv_server_start(srv)
+        st = spmvat.spmv_server_wait(srv, timeout_s)
+        wall = time.perf_counter() - t0
+        if st != spmvat.SPMV_OK:
+            raise RuntimeError("server did not finish in time")
+        res = spmvat.spmv_server_results(srv, len(jobs))
+    finally:
+        spmvat.spmv_server_destroy(srv)
+    return res, wall
+
+
+def summarize(res) -> dict:
+    ok = [r for r in res if r.status == spmvat.SPMV_OK]
+    lat = np.array([r.done_s - r.arrival_s for r in ok])
+    first = min(r.arrival_s for r in res)
+    last = max(r.done_s for r in res)
+    fmts = {}
+    for r in ok:
+        name = spmvat.FORMAT_NAMES.get(r.format, str(r.format))
+        fmts[name] = fmts.get(name, 0) + 1
+    return {"jobs": len(res), "failed": len(res) - len(ok),
+            "jobs_per_s": round(len(res) / (last - first), 2) if last > first else None,
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3) if len(lat) else None,
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3) if len(lat) else None,
+            "mean_ms": round(float(lat.mean()) * 1e3, 3) if len(lat) else None,
+            "span_s": round(last - first, 4), "formats": fmts}
+
+
+def compare(jobs_host, slots, hbm_cap, rate, log=print) -> dict:
+    """Both policies on one trace: burst first (all jobs at t = 0) to find
+    the always-CRS capacity, then Poisson arrivals at `rate` jobs/s (rate
+    'auto': 70% of that capacity)."""
+    table = load_table()
+    out = {"slots": slots, "hbm_cap_bytes": hbm_cap}
+    zeros = [0.0] * len(jobs_host)
+    burst = {}
+    for name, pol in (("crs", 1), ("auto", 0)):
+        res, wall = run(jobs_host, pol, slots, hbm_cap, table, zeros)
+        burst[name] = summarize(res)
+        log(f"[serve] burst {name}: {burst[name]}")
+    out["burst"] = burst
+    if rate == "auto":
+        lam = 0.7 * burst["crs"]["jobs_per_s"]
+    else:
+        lam = float(rate)
+    u = np.random.default_rng(20240700019).random(len(jobs_host))
+    arr = np.cumsum(-np.log1p(-u) / lam)
+    arr -= arr[0]
+    poisson = {}
+    for name, pol in (("crs", 1), ("auto", 0)):
+        res, wall = run(jobs_host, pol, slots, hbm_cap, table, arr.tolist())
+        poisson[name] = summarize(res)
+        log(f"[serve] poisson {name}: {poisson[name]}")
+    out["poisson"] = {"rate_per_s": round(lam, 2), **poisson}
+    return out
+
+
+def main(argv=None):
+    import gen
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--jobs", type=int, default=2048)
+    ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--cap-gb", type=float, default=200.0)
+    ap.add_argument("--rate", default="auto")
+    ap.add_argument("--n-max", type=float, default=5e5)
+    a = ap.parse_args(argv)
+    t0 = time.time()
+    specs = gen.serving_jobs(a.jobs, rate_per_s=0.0, n_max=a.n_max)
+    jobs = build_jobs(specs)
+    print(f"[serve] built {len(jobs)} jobs ({sum(j.nnz for j in jobs) / 1e6:.1f}M nonzeros) in "
+          f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    out = compare(jobs, a.slots, int(a.cap_gb * (1 << 30)), a.rate,
+                  log=lambda s: print(s, file=sys.stderr, flush=True))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -147,3 +147,57 @@ def test_uncalibrated_table_falls_back_to_paper_rule():
     assert why.rule == 0 and f == spmvat.ELL_ROW
     t2 = spmvat.at_table_build([], [], None, 1.0)
     assert math.isinf(t2.d_star)
+
+
+def test_arena_first_fit_and_coalescing():
+    """The server's offset allocator against a plain Python model of
+    first-fit over 256-byte granules with coalescing frees."""
+    spmvat = _lib()
+    L = spmvat.lib()
+    cap = 1 << 20
+    A = L.spmv_arena_create(cap)
+    model = [(0, cap)]                       # sorted free list (offset, size)
+
+    def m_alloc(b):
+        need = max(b, 1)
+        need = (need + 255) // 256 * 256
+        for i, (o, s) in enumerate(model):
+            if s >= need:
+                if s == need:
+                    model.pop(i)
+                else:
+                    model[i] = (o + need, s - need)
+                return o
+        return -1
+
+    def m_free(o, b):
+        s = (max(b, 1) + 255) // 256 * 256
+        model.append((o, s))
+        model.sort()
+        merged = []
+        for seg in model:
+            if merged and merged[-1][0] + merged[-1][1] == seg[0]:
+                merged[-1] = (merged[-1][0], merged[-1][1] + seg[1])
+            else:
+                merged.append(seg)
+        model[:] = merged
+
+    rng = np.random.default_rng(0)
+    live = []
+    for step in range(3000):
+        if live and rng.random() < 0.45:
+            o, b = live.pop(int(rng.integers(0, len(live))))
+            L.spmv_arena_free(A, o, b)
+            m_free(o, b)
+        else:
+            b = int(rng.integers(1, 40000))
+            o = L.spmv_arena_alloc(A, b)
+            assert o == m_alloc(b)
+            if o >= 0:
+                live.append((o, b))
+        assert L.spmv_arena_free_bytes(A) == sum(s for _, s in model)
+        assert L.spmv_arena_largest(A) == max([s for _, s in model] or [0])
+    for o, b in live:
+        L.spmv_arena_free(A, o, b)
+    assert L.spmv_arena_free_bytes(A) == cap and L.spmv_arena_largest(A) == cap
+    L.spmv_arena_destroy(A)
