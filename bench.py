@@ -76,18 +76,21 @@ class Timer:
         self.torch = torch
         self.marks = {}
 
-    def __call__(self, name, fn, *a, **k):
+    def __call__(self, name, fn, *a, reps=1, **k):
+        """Times `reps` back-to-back calls between one pair of events and
+        records the mean per call."""
         t = self.torch
         e0, e1 = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
         e0.record()
-        r = fn(*a, **k)
+        for _ in range(reps):
+            r = fn(*a, **k)
         e1.record()
-        self.marks.setdefault(name, []).append((e0, e1))
+        self.marks.setdefault(name, []).append((e0, e1, reps))
         return r
 
     def results_ms(self):
         self.torch.cuda.synchronize()
-        return {k: [a.elapsed_time(b) for a, b in v] for k, v in self.marks.items()}
+        return {k: [a.elapsed_time(b) / r for a, b, r in v] for k, v in self.marks.items()}
 
     def clear(self):
         self.marks = {}
@@ -137,7 +140,7 @@ class PathRunner:
     """Device buffers for one matrix and one value type, allocated once;
     step() runs the whole path through the C ABI."""
 
-    def __init__(self, spmvat, irp, icol, val, x, label, with_column=True, variants=(0, 1)):
+    def __init__(self, spmvat, irp, icol, val, x, label, with_column=True, variants=(0, 1), spmv_reps=3):
         import torch
         self.sp = spmvat
         self.label = label
@@ -151,6 +154,7 @@ class PathRunner:
         self.xb = x.element_size()
         self.with_column = with_column
         self.variants = variants
+        self.reps = spmv_reps
         self.work = torch.empty(spmvat.spmv_plan_workspace_bytes(self.n, self.nnz), dtype=torch.uint8, device=self.dev)
         self.y = torch.empty_like(x)
         # one plan to size the buffers
@@ -183,13 +187,14 @@ class PathRunner:
             T(f"{L}coo_col", sp.csr_to_coo, plan, 1, self.buf[sp.COO_COL][0])
             T(f"{L}ell_col", sp.csr_to_ell, plan, 1, self.buf[sp.ELL_COL][0])
         T(f"{L}ell_row", sp.csr_to_ell, plan, 0, self.buf[sp.ELL_ROW][0])
+        R = self.reps
         for v in self.variants:
-            T(f"{L}spmv_crs{v}", sp.spmv_exec, plan, sp.CRS, v, self.x, self.y)
-        T(f"{L}spmv_ell_row", sp.spmv_exec, plan, sp.ELL_ROW, 0, self.x, self.y)
-        T(f"{L}spmv_coo_row", sp.spmv_exec, plan, sp.COO_ROW, 0, self.x, self.y)
+            T(f"{L}spmv_crs{v}", sp.spmv_exec, plan, sp.CRS, v, self.x, self.y, reps=R)
+        T(f"{L}spmv_ell_row", sp.spmv_exec, plan, sp.ELL_ROW, 0, self.x, self.y, reps=R)
+        T(f"{L}spmv_coo_row", sp.spmv_exec, plan, sp.COO_ROW, 0, self.x, self.y, reps=R)
         if self.with_column and not spmv_only:
-            T(f"{L}spmv_coo_col", sp.spmv_exec, plan, sp.COO_COL, 0, self.x, self.y)
-            T(f"{L}spmv_ell_col", sp.spmv_exec, plan, sp.ELL_COL, 0, self.x, self.y)
+            T(f"{L}spmv_coo_col", sp.spmv_exec, plan, sp.COO_COL, 0, self.x, self.y, reps=R)
+            T(f"{L}spmv_ell_col", sp.spmv_exec, plan, sp.ELL_COL, 0, self.x, self.y, reps=R)
         sp.spmv_plan_destroy(plan)
 
     def outputs(self, fmt, variant=0):
@@ -216,6 +221,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-precision", action="store_true", help="skip the reduced-precision rows")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-oracle SpMV sample")
+    ap.add_argument("--spmv-reps", type=int, default=3,
+                    help="back-to-back SpMVs per format in each step (one event pair around them)")
+    ap.add_argument("--serve-jobs", type=int, default=256,
+                    help="jobs of the serving stream replayed after the timed steps (0: skip)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one 1 GiB device copy first (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
@@ -255,12 +264,13 @@ def main():
     while wsub < 64 and wsub < mu:
         wsub *= 2
     v_sub = 1 + int(math.log2(wsub))          # explicit lane-group variant of that width
-    runners = [PathRunner(spmvat, irp, icol, val, xd, "", variants=(0, v_sub, 8))]
+    runners = [PathRunner(spmvat, irp, icol, val, xd, "", variants=(0, v_sub, 8), spmv_reps=args.spmv_reps)]
     if not args.no_precision:
         x32 = xd.float()
         for dt, tag in ((spmvat.F32, "f32"), (spmvat.BF16, "bf16")):
             v = spmvat.convert_values(val, dt)
-            runners.append(PathRunner(spmvat, irp, icol, v, x32, f"{tag}:", with_column=False, variants=(8,)))
+            runners.append(PathRunner(spmvat, irp, icol, v, x32, f"{tag}:", with_column=False, variants=(8,),
+                                      spmv_reps=args.spmv_reps))
     table, table_path = load_at_table(spmvat)
     torch.cuda.synchronize()
 
@@ -284,7 +294,9 @@ def main():
         one_step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    ms = {k: statistics.mean(v) for k, v in T.results_ms().items()}
+    raw = T.results_ms()
+    ms = {k: statistics.mean(v) for k, v in raw.items()}
+    med = {k: statistics.median(v) for k, v in raw.items()}
     ms_per_step = 1000.0 * wall / args.steps
     log(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step")
 
@@ -303,15 +315,16 @@ def main():
     for name, (fmt, key, width) in spmv_names.items():
         b = spmv_bytes(fmt, n, nnz, width, 8, 8)
         g = gbs(b, ms[key])
-        per_format[name] = {"us": round(ms[key] * 1e3, 2), "gbs": round(g, 1), "frac": round(g / HBM_PEAK_GBS, 4),
-                            "bytes": int(b)}
+        per_format[name] = {"us": round(ms[key] * 1e3, 2), "median_us": round(med[key] * 1e3, 2), "gbs": round(g, 1),
+                            "frac": round(g / HBM_PEAK_GBS, 4), "bytes": int(b)}
     best = max(per_format, key=lambda k: per_format[k]["gbs"])
     t_crs0 = ms["spmv_crs0"]
     t_crs1 = min(ms["spmv_crs8"], ms[f"spmv_crs{v_sub}"])      # the strong CRS kernel
     transforms = {}
     for kind, width in (("stats", 0), ("coo_row", 0), ("ccs", 0), ("coo_col", 0), ("ell_row", w), ("ell_col", wc)):
         b = transform_bytes(kind, n, nnz, width, 8)
-        transforms[kind] = {"us": round(ms[kind] * 1e3, 2), "gbs": round(gbs(b, ms[kind]), 1),
+        transforms[kind] = {"us": round(ms[kind] * 1e3, 2), "median_us": round(med[kind] * 1e3, 2),
+                            "gbs": round(gbs(b, ms[kind]), 1),
                             "tt_vs_crs_scalar": round(ms[kind] / t_crs0, 3),
                             "tt_vs_crs_best": round(ms[kind] / t_crs1, 3), "bytes": int(b)}
     sp_ell = {"vs_crs_scalar": round(t_crs0 / ms["spmv_ell_row"], 3),
@@ -332,7 +345,8 @@ def main():
                 y = r.outputs(code, var)
                 err = float(np.linalg.norm(y - y64) / np.linalg.norm(y64))
                 entry[fmt if fmt != "crs" else "crs_stream"] = {
-                    "us": round(t_ms * 1e3, 2), "gbs": round(gbs(b_, t_ms), 1), "frac": round(gbs(b_, t_ms) / HBM_PEAK_GBS, 4),
+                    "us": round(t_ms * 1e3, 2), "median_us": round(med[f"{tag}:{key}"] * 1e3, 2),
+                    "gbs": round(gbs(b_, t_ms), 1), "frac": round(gbs(b_, t_ms) / HBM_PEAK_GBS, 4),
                     "speedup_vs_f64": round(ms[key] / t_ms, 3), "rel_l2_vs_f64": float(f"{err:.3e}")}
             entry["convert_us"] = round(ms[f"{tag}:convert"] * 1e3, 2)
             precision[tag] = entry
@@ -369,9 +383,26 @@ def main():
                         "choice": spmvat.FORMAT_NAMES[r0.decision[0]] if hasattr(r0, "decision") else None},
         "precision": precision,
     }
+    if args.serve_jobs > 0:
+        out["serving"] = serving(args.serve_jobs)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(m, x64, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def serving(count):
+    """The serving stream (first `count` jobs), replayed through the
+    continuous-batching server, auto-tuned vs always-CRS (binary32)."""
+    import gen
+    from paper_2407_00019_amd import serve
+    t0 = time.time()
+    jobs = serve.build_jobs(gen.serving_jobs(count, rate_per_s=0.0))
+    log(f"[bench] serving: built {count} jobs ({sum(j.nnz for j in jobs) / 1e6:.0f}M nonzeros) "
+        f"in {time.time() - t0:.1f}s")
+    res = serve.compare(jobs, slots=8, hbm_cap=200 << 30, rate="auto", log=log)
+    res["jobs_of_stream"] = count
+    res["nnz_total"] = int(sum(j.nnz for j in jobs))
+    return res
 
 
 def kernel_source_sha():
