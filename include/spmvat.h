@@ -193,11 +193,11 @@ spmv_status csr_to_ell(spmv_plan *p, int column_wise, const spmv_buffers *out,
  * format f (section 3, Figs. 1-3, and CRS itself).  x[n] and y[n] are
  * device arrays: F64 for F64 values, else F32 (accumulation in F32).
  * variant (CRS only): 0 one thread per row (the plain CRS loop); 1 the
- * library's choice: the stream kernel when no row exceeds 256 entries, else
- * a lane group per row sized from the mean row length; 2..7 a group of
+ * library's CRS kernel, currently the stream kernel; 2..7 a group of
  * 2^(variant-1) lanes per row; 8 the stream kernel (a workgroup stages the
- * products of 256 consecutive rows in LDS and each thread sums its row in
- * storage order).  Other formats take variant 0.
+ * products of 256 consecutive rows in LDS; each thread sums its own row in
+ * storage order, the workgroup reduces rows of more than 256 entries).
+ * Other formats take variant 0.
  * Determinism: CRS, COO_ROW and ELL_ROW are deterministic run to run;
  * COO_COL and ELL_COL scatter with atomics and are not.  x and y must not
  * overlap.  SPMV_E_NOT_READY when the format has not been built. */

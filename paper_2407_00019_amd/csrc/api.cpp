@@ -83,17 +83,6 @@ bool check_buffers(const spmv_buffers* out, int count, const spmv_sizes& need) {
     return true;
 }
 
-int auto_vector_width(const spmv_plan* p) {
-    // smallest power of two covering the mean row length, within [2, 64]
-    int w = 2;
-    while (w < 64 && (double)w < p->st.mu) w <<= 1;
-    return w;
-}
-
-// Rows up to this length go to the LDS-staged stream kernel under the
-// automatic CRS variant; longer rows would serialise one thread.
-constexpr int32_t kStreamMaxRow = 256;
-
 }  // namespace
 
 // ------------------------------------------------------------------ plan
@@ -354,11 +343,11 @@ SPMV_API spmv_status spmv_exec(const spmv_plan* p, spmv_format f, int variant, c
     switch (f) {
         case SPMV_CRS: {
             if (variant < 0 || variant > 8) return SPMV_E_ARG;
-            const bool stream = variant == 8 || (variant == 1 && p->st.max_row <= kStreamMaxRow);
+            const bool stream = variant == 8 || variant == 1;
             if (variant == 0) HIP_TRY(p, launch_spmv_crs_scalar(dt, p->n, p->irp, p->icol, p->val, x, y, s));
             else if (stream) HIP_TRY(p, launch_spmv_crs_stream(dt, p->n, p->irp, p->icol, p->val, x, y, s));
             else {
-                const int w = variant == 1 ? auto_vector_width(p) : (1 << (variant - 1));
+                const int w = 1 << (variant - 1);
                 HIP_TRY(p, launch_spmv_crs_vector(dt, w, p->n, p->irp, p->icol, p->val, x, y, s));
             }
             return SPMV_OK;

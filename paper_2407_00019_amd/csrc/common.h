@@ -49,6 +49,29 @@ template <> __device__ __forceinline__ f16_t ld_nt(const f16_t* p) {
     return r;
 }
 
+// Two consecutive elements through one non-temporal load (p must be aligned
+// to twice the element size).
+template <typename T>
+__device__ __forceinline__ void load2_nt(const T* p, T& a, T& b) {
+    if constexpr (sizeof(T) == 8) {
+        typedef unsigned long long v2 __attribute__((ext_vector_type(2)));
+        const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+        const unsigned long long lo = v.x, hi = v.y;
+        __builtin_memcpy(&a, &lo, 8);
+        __builtin_memcpy(&b, &hi, 8);
+    } else if constexpr (sizeof(T) == 4) {
+        const unsigned long long v = __builtin_nontemporal_load(reinterpret_cast<const unsigned long long*>(p));
+        const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+        __builtin_memcpy(&a, &lo, 4);
+        __builtin_memcpy(&b, &hi, 4);
+    } else {
+        const uint32_t v = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p));
+        const uint16_t lo = (uint16_t)v, hi = (uint16_t)(v >> 16);
+        __builtin_memcpy(&a, &lo, 2);
+        __builtin_memcpy(&b, &hi, 2);
+    }
+}
+
 // Raw element types used when values are only moved (transformations).
 template <int B> struct raw_of;
 template <> struct raw_of<8> { using type = uint64_t; };

@@ -8,7 +8,8 @@
 //  CRS stream     a workgroup takes 256 rows; their entries, contiguous in
 //                 CRS, are read coalesced in chunks and their products kept
 //                 in LDS; each row is then summed by its own thread in
-//                 storage order.
+//                 storage order, except rows of more than 256 entries, which
+//                 the whole workgroup reduces.
 //  ELL-Row        Fig. 3: thread per row, slot loop inside, slot-major loads
 //                 coalesced across the wave; no reduction step.
 //  ELL-Column     thread per column, y(row) += val * x(col) with atomics.
@@ -58,6 +59,7 @@ k_spmv_crs_vector(int n, const int* __restrict__ irp, const int* __restrict__ ic
 }
 
 constexpr int kStreamCap = 2048;   // products staged in LDS per chunk
+constexpr int kStreamLong = 256;   // rows longer than this are summed by the whole workgroup
 
 template <typename V, typename X>
 __global__ void __launch_bounds__(kBlock)
@@ -65,6 +67,8 @@ k_spmv_crs_stream(int n, const int* __restrict__ irp, const int* __restrict__ ic
                   const X* __restrict__ x, X* __restrict__ y) {
     __shared__ X prod[kStreamCap];
     __shared__ int sp[kBlock + 1];
+    __shared__ unsigned long long s_long[kBlock / kWave];
+    __shared__ X s_red[kBlock / kWave];
     const int r0 = (int)xcd_block(blockIdx.x, gridDim.x) * kBlock;
     const int rows = min(kBlock, n - r0);
     const int t = threadIdx.x;
@@ -72,6 +76,13 @@ k_spmv_crs_stream(int n, const int* __restrict__ irp, const int* __restrict__ ic
     __syncthreads();
     const int end = sp[rows];
     const int a = t < rows ? sp[t] : end, b = t < rows ? sp[t + 1] : end;
+    const bool lng = (b - a) > kStreamLong;
+    const unsigned long long m = __ballot(lng);
+    if ((t & (kWave - 1)) == 0) s_long[t / kWave] = m;
+    __syncthreads();
+    bool any_long = false;
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; ++w) any_long |= s_long[w] != 0;
     X s = 0;
     for (int c0 = sp[0]; c0 < end; c0 += kStreamCap) {
         const int cl = min(kStreamCap, end - c0);
@@ -79,8 +90,35 @@ k_spmv_crs_stream(int n, const int* __restrict__ irp, const int* __restrict__ ic
         for (int q = t; q < cl; q += kBlock)
             prod[q] = (X)widen(ld_nt(&val[c0 + q])) * x[ld_nt(&icol[c0 + q])];
         __syncthreads();
-        const int lo = max(a, c0), hi = min(b, c0 + cl);
-        for (int p = lo; p < hi; ++p) s += prod[p - c0];
+        if (!lng) {
+            const int lo = max(a, c0), hi = min(b, c0 + cl);
+            for (int p = lo; p < hi; ++p) s += prod[p - c0];
+        }
+        if (any_long) {
+            // each long row in turn: the workgroup sums its part of the chunk
+            for (int w = 0; w < kBlock / kWave; ++w) {
+                unsigned long long bits = s_long[w];
+                while (bits) {
+                    const int r = w * kWave + __ffsll((long long)bits) - 1;
+                    bits &= bits - 1;
+                    const int lo = max(sp[r], c0) - c0, hi = min(sp[r + 1], c0 + cl) - c0;
+                    if (lo >= hi) continue;
+                    X part = 0;
+                    for (int q = lo + t; q < hi; q += kBlock) part += prod[q];
+#pragma unroll
+                    for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off, kWave);
+                    if ((t & (kWave - 1)) == 0) s_red[t / kWave] = part;
+                    __syncthreads();
+                    if (t == r) {
+                        X tot = 0;
+#pragma unroll
+                        for (int k2 = 0; k2 < kBlock / kWave; ++k2) tot += s_red[k2];
+                        s += tot;
+                    }
+                    __syncthreads();
+                }
+            }
+        }
         __syncthreads();
     }
     if (t < rows) y[r0 + t] = s;
@@ -100,6 +138,29 @@ k_spmv_ell_row(int n, int width, const V* __restrict__ ev, const int* __restrict
     for (int k = 0; k < width; ++k, off += (size_t)n)
         s += (X)widen(ld_nt(&ev[off])) * x[ld_nt(&ec[off])];
     y[i] = s;
+}
+
+// Two consecutive rows per thread: one 2-element load per slot for values
+// and indices (n even keeps every k*n + i pair aligned).
+template <typename V, typename X>
+__global__ void __launch_bounds__(kBlock)
+k_spmv_ell_row2(int n, int width, const V* __restrict__ ev, const int* __restrict__ ec, const X* __restrict__ x,
+                X* __restrict__ y) {
+    const int i = ((int)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) * 2;
+    if (i >= n) return;
+    X s0 = 0, s1 = 0;
+    size_t off = (size_t)i;
+#pragma unroll 8
+    for (int k = 0; k < width; ++k, off += (size_t)n) {
+        V v0, v1;
+        int c0, c1;
+        load2_nt(&ev[off], v0, v1);
+        load2_nt(&ec[off], c0, c1);
+        s0 += (X)widen(v0) * x[c0];
+        s1 += (X)widen(v1) * x[c1];
+    }
+    y[i] = s0;
+    y[i + 1] = s1;
 }
 
 template <typename V, typename X>
@@ -398,8 +459,15 @@ hipError_t launch_spmv_crs_vector(int dtype, int width, int n, const int* irp, c
 
 hipError_t launch_spmv_ell_row(int dtype, int n, int width, const void* ev, const int* ec, const void* x,
                                void* y, hipStream_t s) {
-    SPMV_DISPATCH(dtype, hipLaunchKernelGGL((k_spmv_ell_row<V, X>), dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s,
-                                            n, width, (const V*)ev, ec, (const X*)x, (X*)y));
+    if (dtype == 0 && n % 2 == 0) {
+        // binary64: two rows per thread measured faster; narrower values lose
+        // parallelism without gaining wider loads, so they keep one row
+        hipLaunchKernelGGL((k_spmv_ell_row2<double, double>), dim3(grid_for(n / 2, kBlock)), dim3(kBlock), 0, s, n,
+                           width, (const double*)ev, ec, (const double*)x, (double*)y);
+    } else {
+        SPMV_DISPATCH(dtype, hipLaunchKernelGGL((k_spmv_ell_row<V, X>), dim3(grid_for(n, kBlock)), dim3(kBlock), 0,
+                                                s, n, width, (const V*)ev, ec, (const X*)x, (X*)y));
+    }
     return hipGetLastError();
 }
 

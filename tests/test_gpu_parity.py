@@ -115,7 +115,10 @@ def test_small_matrices_full_path(name, builder):
         assert oracle.rel_l2(y, yref) <= TOL64, (name, key, oracle.rel_l2(y, yref))
 
 
-@pytest.mark.parametrize("name,builder", SMALL[:6], ids=[s[0] for s in SMALL[:6]])
+INTEGER_CASES = SMALL[:6] + [s for s in SMALL if s[0] in ("powerlaw_small", "banded")]
+
+
+@pytest.mark.parametrize("name,builder", INTEGER_CASES, ids=[s[0] for s in INTEGER_CASES])
 def test_integer_data_is_bitwise_exact(name, builder):
     m = builder()
     rng = np.random.default_rng(3)
