@@ -119,20 +119,7 @@ def load_at_table(spmvat):
     path = os.path.join(ROOT, "paper_2407_00019_amd", "at_table.json")
     if os.path.exists(path):
         with open(path) as f:
-            d = json.load(f)
-        t = spmvat.at_table_build(d.get("d", []), d.get("r", []), d.get("feasible"), d.get("c", 1.0))
-        cm = d.get("cost_model")
-        if cm:
-            t.calibrated = 1
-            for f_, per_v in cm["spmv_bps"].items():
-                for v_, buckets in enumerate(per_v):
-                    for b_, val in enumerate(buckets):
-                        t.spmv_bps[int(f_)][v_][b_] = val
-            for f_, buckets in cm["trans_bps"].items():
-                for b_, val in enumerate(buckets):
-                    t.trans_bps[int(f_)][b_] = val
-            t.launch_s = cm.get("launch_s", 0.0)
-        return t, path
+            return spmvat.at_table_from_json(json.load(f)), path
     return spmvat.at_table_build([], [], None, 1.0), None
 
 

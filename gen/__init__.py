@@ -51,6 +51,7 @@ def _lib():
         lib.gen_lengths_to_irp.argtypes = [i32, P, P]
         lib.gen_lengths_to_irp.restype = i64
         lib.gen_random_cols.argtypes = [i32, i32, P, u64, P]
+        lib.gen_window_cols.argtypes = [i32, i32, P, u64, P]
         lib.gen_banded.argtypes = [i32, i32, u64, P, P, P]
         lib.gen_banded.restype = i64
         lib.gen_unif_stream.argtypes = [i64, u64, u64, P]
@@ -137,6 +138,25 @@ def random_rows(n: int, lengths: np.ndarray, seed: int) -> Crs:
         raise ValueError("nnz exceeds the int32 range")
     icol = np.empty(nnz, np.int32)
     lib.gen_random_cols(n, n, _p(irp), seed, _p(icol))
+    val = normal(nnz, seed)
+    return Crs(n, irp, icol, val)
+
+
+def window_rows(n: int, lengths: np.ndarray, window: int, seed: int) -> Crs:
+    """Rows with the given lengths, columns uniform without replacement from
+    [i - window, i + window] (clipped), sorted; values N(0,1)."""
+    lib = _lib()
+    lengths = np.ascontiguousarray(lengths, dtype=np.int32)
+    idx = np.arange(n)
+    room = (np.minimum(idx + window, n - 1) - np.maximum(idx - window, 0) + 1).astype(np.int32)
+    if np.any(lengths > room):
+        raise ValueError("a row is longer than its column window")
+    irp = np.empty(n + 1, np.int32)
+    nnz = lib.gen_lengths_to_irp(n, _p(lengths), _p(irp))
+    if nnz < 0:
+        raise ValueError("nnz exceeds the int32 range")
+    icol = np.empty(nnz, np.int32)
+    lib.gen_window_cols(n, window, _p(irp), seed, _p(icol))
     val = normal(nnz, seed)
     return Crs(n, irp, icol, val)
 
@@ -234,11 +254,24 @@ def dsweep_lengths(s: float, n: int = DSWEEP_N) -> np.ndarray:
     return lognormal_lengths(n, 32.0, s, 1, 8192, seed_for(5))
 
 
-def dsweep_matrix(index: int, n: int = DSWEEP_N) -> Crs:
+DSWEEP_WINDOW = 4096
+
+
+def dsweep_matrix(index: int, n: int = DSWEEP_N, local: bool = False) -> Crs:
+    """Sweep matrix `index`: uniform columns over the whole row (default) or
+    over the window [i - 4096, i + 4096] around the row (local=True, the
+    banded-structure family; lengths clipped to the window)."""
     tab = dsweep_table()
     s = float(tab["s"][index])
-    m = random_rows(n, dsweep_lengths(s, n), seed_for(5, index))
-    m.name = f"dsweep_{index}_D{DSWEEP_TARGETS[index]:.3f}"
+    lens = dsweep_lengths(s, n)
+    if local:
+        idx = np.arange(n)
+        room = np.minimum(idx + DSWEEP_WINDOW, n - 1) - np.maximum(idx - DSWEEP_WINDOW, 0) + 1
+        lens = np.minimum(lens, room).astype(np.int32)
+        m = window_rows(n, lens, DSWEEP_WINDOW, seed_for(5, 500 + index))
+    else:
+        m = random_rows(n, lens, seed_for(5, index))
+    m.name = f"dsweep{'_local' if local else ''}_{index}_D{DSWEEP_TARGETS[index]:.3f}"
     return m
 
 

@@ -241,6 +241,54 @@ void gen_random_cols(int32_t n, int32_t ncols, const int32_t *irp, uint64_t seed
     }
 }
 
+/* Column indices drawn uniformly without replacement from the window
+ * [i - w, i + w] (clipped to [0, n-1]) around each row i, then sorted.
+ * Row lengths must not exceed the clipped window.  Same counter layout as
+ * gen_random_cols. */
+void gen_window_cols(int32_t n, int32_t w, const int32_t *irp, uint64_t seed, int32_t *icol)
+{
+#pragma omp parallel
+    {
+        int32_t cap = 0;
+        int32_t *set = NULL;
+#pragma omp for schedule(dynamic, 4096)
+        for (int32_t i = 0; i < n; ++i) {
+            int32_t k = irp[i + 1] - irp[i];
+            if (k == 0) continue;
+            int64_t lo = (int64_t)i - w < 0 ? 0 : (int64_t)i - w;
+            int64_t hi = (int64_t)i + w > n - 1 ? n - 1 : (int64_t)i + w;
+            int64_t span = hi - lo + 1;
+            int32_t need = 4;
+            while (need < 2 * k) need <<= 1;
+            if (need > cap) {
+                free(set);
+                cap = need;
+                set = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+            }
+            for (int32_t t = 0; t < cap; ++t) set[t] = -1;
+            int32_t *out = icol + irp[i];
+            int32_t m = 0;
+            uint64_t base = (uint64_t)i << 32;
+            for (int64_t j = span - k; j < span; ++j) {
+                int32_t t = (int32_t)below(seed, ST_COL, base + (uint64_t)(j - (span - k)), (uint64_t)j + 1);
+                int32_t cand = t;
+                for (int pass = 0; pass < 2; ++pass) {
+                    uint32_t h = ((uint32_t)cand * 2654435761u) & (uint32_t)(cap - 1);
+                    int found = 0;
+                    while (set[h] != -1) {
+                        if (set[h] == cand) { found = 1; break; }
+                        h = (h + 1) & (uint32_t)(cap - 1);
+                    }
+                    if (!found) { set[h] = cand; out[m++] = (int32_t)(lo + cand); break; }
+                    cand = (int32_t)j;
+                }
+            }
+            qsort(out, (size_t)k, sizeof(int32_t), cmp_i32);
+        }
+        free(set);
+    }
+}
+
 /* Banded pattern: row i holds columns max(0,i-b) .. min(n-1,i+b).
  * Values U[-1,1) per entry.  Returns nnz; fills non-NULL arrays. */
 int64_t gen_banded(int32_t n, int32_t b, uint64_t seed, int32_t *irp, int32_t *icol, double *val)

@@ -64,12 +64,14 @@ typedef struct spmv_plan spmv_plan;
  * nnz = 0), each rounded once from the exact integers: with
  * num = n*sum_len2 - sum_len^2 rounded to binary64, sigma = sqrt(num) / n and
  * d_mat = sqrt(num) / sum_len.  max_col is the longest column (the ELL-Column
- * width), -1 until csr_to_ccs has run. */
+ * width), -1 until csr_to_ccs has run.  bandwidth is the matrix bandwidth
+ * max |i - j| over every stored entry (0 for nnz = 0): the locality feature
+ * of the cost model, not part of the paper. */
 typedef struct {
     int32_t n;
     int64_t nnz;
     int64_t sum_len, sum_len2;
-    int32_t max_row, min_row, max_col;
+    int32_t max_row, min_row, max_col, bandwidth;
     double mu, sigma, d_mat;
 } spmv_stats;
 
@@ -95,17 +97,20 @@ typedef struct {
 } spmv_buffers;
 
 /* Auto-tuning table: the off-line phase's result (section 2.2) plus a cost
- * model for the amortised (k-aware) decision.  D bucket b = min(7,
- * floor(D_mat / 0.5)).  Rates are algorithmic bytes per second; 0 marks a
- * missing entry. */
+ * model for the amortised (k-aware) decision, indexed by a locality class
+ * (0: bandwidth <= AT_LOCAL_BAND, the x entries a row gathers lie close to
+ * it; 1: scattered) and a D_mat bucket b = the number of the edges 1/16,
+ * 1/8, 1/4, 1/2, 1, 2, 4 that D_mat reaches.  Rates are algorithmic bytes
+ * per second; 0 marks a missing entry. */
 #define AT_DBUCKETS 8
+#define AT_LOCAL_BAND 65536
 typedef struct {
-    double c;                              /* R_ell threshold (the paper uses 1.0) */
-    double d_star;                         /* ELL-Row when D_mat < d_star; +inf: always */
-    int32_t calibrated;                    /* 1 when the cost model is filled */
-    double spmv_bps[6][2][AT_DBUCKETS];    /* [format][variant][bucket] SpMV rate */
-    double trans_bps[6][AT_DBUCKETS];      /* [format][bucket] transformation rate */
-    double launch_s;                       /* fixed cost added per kernel launch */
+    double c;                                 /* R_ell threshold (the paper uses 1.0) */
+    double d_star;                            /* ELL-Row when D_mat < d_star; +inf: always */
+    int32_t calibrated;                       /* 1 when the cost model is filled */
+    double spmv_bps[2][6][2][AT_DBUCKETS];    /* [locality][format][variant][bucket] SpMV rate */
+    double trans_bps[2][6][AT_DBUCKETS];      /* [locality][format][bucket] transformation rate */
+    double launch_s;                          /* fixed cost added per kernel launch */
 } at_table;
 
 typedef struct {

@@ -43,6 +43,8 @@ def _lib():
         lib.orc_validate_crs.argtypes = [i32, i64, P, P]
         lib.orc_validate_crs.restype = ctypes.c_int
         lib.orc_row_moments.argtypes = [i32, P, P, P, P, P]
+        lib.orc_bandwidth.argtypes = [i32, P, P]
+        lib.orc_bandwidth.restype = i32
         lib.orc_u128_to_double.argtypes = [u64, u64]
         lib.orc_u128_to_double.restype = f64
         lib.orc_dmat.argtypes = [i32, i64, i64, P, P, P]
@@ -99,6 +101,12 @@ def row_moments(n, irp):
     hi, lo = ctypes.c_int32(), ctypes.c_int32()
     _lib().orc_row_moments(n, _p(irp), ctypes.byref(s1), ctypes.byref(s2), ctypes.byref(hi), ctypes.byref(lo))
     return s1.value, s2.value, hi.value, lo.value
+
+
+def bandwidth(n, irp, icol) -> int:
+    """Matrix bandwidth: the largest |i - j| over every stored entry (a
+    locality feature of the cost model, not part of the paper)."""
+    return int(_lib().orc_bandwidth(n, _p(_i32(irp)), _p(_i32(icol))))
 
 
 def u128_to_double(v: int) -> float:

@@ -62,6 +62,22 @@ void orc_row_moments(int32_t n, const int32_t *irp, int64_t *s1, int64_t *s2,
     *lmin = (n > 0) ? lo : 0;
 }
 
+/* Locality of a CRS matrix (a cost-model feature, not part of the paper):
+ * the matrix bandwidth, the largest |i - j| over every stored entry a_ij
+ * (0 when there is none). */
+int32_t orc_bandwidth(int32_t n, const int32_t *irp, const int32_t *icol)
+{
+    int64_t w = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t p = irp[i]; p < irp[i + 1]; ++p) {
+            int64_t d = (int64_t)icol[p] - i;
+            if (d < 0) d = -d;
+            if (d > w) w = d;
+        }
+    }
+    return (int32_t)w;
+}
+
 /* Nearest binary64 to a non-negative 128-bit integer, ties to even. */
 double orc_u128_to_double(uint64_t hi, uint64_t lo)
 {

@@ -31,6 +31,8 @@ FORMAT_NAMES = {CRS: "crs", COO_ROW: "coo_row", CCS: "ccs", COO_COL: "coo_col", 
 DTYPE_OF_TORCH = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16}
 TORCH_OF_DTYPE = {v: k for k, v in DTYPE_OF_TORCH.items()}
 AT_DBUCKETS = 8
+AT_LOCAL_BAND = 65536
+AT_DBUCKET_EDGES = (0.0625, 0.125, 0.25, 0.5, 1.0, 2.0, 4.0)
 
 
 class SpmvError(RuntimeError):
@@ -45,7 +47,8 @@ class SpmvError(RuntimeError):
 class spmv_stats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("sum_len", ctypes.c_int64),
                 ("sum_len2", ctypes.c_int64), ("max_row", ctypes.c_int32), ("min_row", ctypes.c_int32),
-                ("max_col", ctypes.c_int32), ("mu", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("max_col", ctypes.c_int32), ("bandwidth", ctypes.c_int32), ("mu", ctypes.c_double),
+                ("sigma", ctypes.c_double),
                 ("d_mat", ctypes.c_double)]
 
 
@@ -59,8 +62,8 @@ class spmv_buffers(ctypes.Structure):
 
 class at_table(ctypes.Structure):
     _fields_ = [("c", ctypes.c_double), ("d_star", ctypes.c_double), ("calibrated", ctypes.c_int32),
-                ("spmv_bps", ((ctypes.c_double * AT_DBUCKETS) * 2) * 6),
-                ("trans_bps", (ctypes.c_double * AT_DBUCKETS) * 6), ("launch_s", ctypes.c_double)]
+                ("spmv_bps", (((ctypes.c_double * AT_DBUCKETS) * 2) * 6) * 2),
+                ("trans_bps", ((ctypes.c_double * AT_DBUCKETS) * 6) * 2), ("launch_s", ctypes.c_double)]
 
 
 class spmv_server_config(ctypes.Structure):
@@ -321,6 +324,28 @@ def spmv_server_destroy(srv) -> None:
 
 
 # ---------------------------------------------------------- convenience
+
+def at_table_from_json(d: dict) -> at_table:
+    """An at_table from the off-line phase's JSON (see offline.py)."""
+    t = at_table_build(d.get("d", []), d.get("r", []), d.get("feasible"), d.get("c", 1.0))
+    cm = d.get("cost_model")
+    if cm:
+        if not isinstance(cm.get("spmv_bps"), list) or len(cm["spmv_bps"]) != 2:
+            raise ValueError("cost_model must hold one entry per locality class (local, scattered); "
+                             "re-run the off-line phase")
+        t.calibrated = 1
+        for loc, per_f in enumerate(cm["spmv_bps"]):
+            for f_, per_v in per_f.items():
+                for v_, buckets in enumerate(per_v):
+                    for b_, val in enumerate(buckets):
+                        t.spmv_bps[loc][int(f_)][v_][b_] = val
+        for loc, per_f in enumerate(cm["trans_bps"]):
+            for f_, buckets in per_f.items():
+                for b_, val in enumerate(buckets):
+                    t.trans_bps[loc][int(f_)][b_] = val
+        t.launch_s = cm.get("launch_s", 0.0)
+    return t
+
 
 def convert_values(val64: torch.Tensor, to: int, stream=None) -> torch.Tensor:
     """binary64 device values -> a new tensor of the storage type `to`."""

@@ -54,13 +54,29 @@ size_t crs_bytes(const spmv_plan* p) {
     return (size_t)(p->n + 1) * 4 + (size_t)p->nnz * (4 + (size_t)vbytes_of(p->dt));
 }
 
-// CCS workspace layout.
+// CCS workspace layout.  n <= 2^22: the two-level counting sort (count
+// table, its chunk sums, summary, level-1 keys and values); larger n: column
+// counts, scatter of (position, row) keys and per-column sorts.
+bool ccs_bucketed(int32_t n) { return n <= (1 << kCcsRowBits); }
+
 struct CcsWs {
-    size_t cursor, bsum, mid, lng, sum, keys, tmp, total;
+    size_t cursor, bsum, mid, lng, sum, keys, tmp;   // per-column sort path
+    size_t table, csum, bkey, bval;                  // bucketed path
+    size_t total;
 };
-CcsWs ccs_ws(int32_t n, int64_t nnz) {
+CcsWs ccs_ws(int32_t n, int64_t nnz, int vb) {
     CcsWs w{};
     size_t o = 0;
+    if (ccs_bucketed(n)) {
+        const CcsGeom g = ccs_geom(n);
+        w.table = o; o += round_up((size_t)g.table * 4, kAlign);
+        w.csum = o;  o += round_up((size_t)g.chunks * 4, kAlign);
+        w.sum = o;   o += round_up(sizeof(ColSummary), kAlign);
+        w.bkey = o;  o += round_up((size_t)nnz * 4, kAlign);
+        w.bval = o;  o += round_up((size_t)nnz * vb, kAlign);
+        w.total = o;
+        return w;
+    }
     w.cursor = o; o += round_up((size_t)n * 4, kAlign);
     w.bsum = o;   o += round_up(col_scan_bsum_count(n) * 8, kAlign);
     const size_t nmid = std::min<size_t>((size_t)n, (size_t)(nnz / (kSortSmall + 1)) + 1);
@@ -115,7 +131,7 @@ spmv_status plan_finish(spmv_plan* p, const RowStats& rs) {
     spmv_stats& st = p->st;
     st.n = n; st.nnz = p->nnz;
     st.sum_len = (int64_t)rs.s1; st.sum_len2 = (int64_t)rs.s2;
-    st.max_row = rs.max_len; st.min_row = (int32_t)rs.min_len; st.max_col = -1;
+    st.max_row = rs.max_len; st.min_row = (int32_t)rs.min_len; st.max_col = -1; st.bandwidth = rs.max_band;
     // Eq. (4) from the exact integer moments: num = n*s2 - s1^2 (= n^2 sigma^2),
     // rounded once; sigma = sqrt(num)/n, D_mat = sqrt(num)/s1.
     const unsigned __int128 num = (unsigned __int128)(uint64_t)n * (uint64_t)rs.s2 -
@@ -203,7 +219,7 @@ SPMV_API spmv_status spmv_buffer_sizes(const spmv_plan* p, spmv_format f, spmv_s
             out->bytes[0] = (n + 1) * 4;
             out->bytes[1] = nnz * 4;
             out->bytes[2] = nnz * vb;
-            out->workspace = ccs_ws(p->n, p->nnz).total;
+            out->workspace = ccs_ws(p->n, p->nnz, vbytes_of(p->dt)).total;
             return SPMV_OK;
         case SPMV_COO_COL:
             out->bytes[0] = nnz * 4;
@@ -255,25 +271,49 @@ SPMV_API spmv_status csr_to_ccs(spmv_plan* p, const spmv_buffers* out, void* wor
     if (need.bytes[0] + need.bytes[1] + need.bytes[2] > p->limit) return SPMV_E_TOO_LARGE;
     if (!work || !aligned16(work) || work_bytes < need.workspace) return SPMV_E_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const CcsWs w = ccs_ws(p->n, p->nnz);
+    const int vb = vbytes_of(p->dt);
+    const CcsWs w = ccs_ws(p->n, p->nnz, vb);
     char* base = static_cast<char*>(work);
+    int32_t* ccp = static_cast<int32_t*>(out->ptr[0]);
+    int32_t* irow_t = static_cast<int32_t*>(out->ptr[1]);
+    void* val_t = out->ptr[2];
+    ColSummary* dsum = reinterpret_cast<ColSummary*>(base + w.sum);
+    ColSummary cs{};
+
+    if (ccs_bucketed(p->n)) {
+        // level 1 (count table, its scan, ordered distribution to column
+        // blocks) and level 2 (ordered placement inside each block); one sync
+        // at the end for the longest column
+        const CcsGeom g = ccs_geom(p->n);
+        HIP_TRY(p, launch_ccs_bucketed(g, p->n, p->nnz, p->irp, p->icol, p->val, vb,
+                                       reinterpret_cast<int32_t*>(base + w.table),
+                                       reinterpret_cast<int32_t*>(base + w.csum),
+                                       reinterpret_cast<uint32_t*>(base + w.bkey), base + w.bval, ccp, irow_t, val_t,
+                                       dsum, s));
+        HIP_TRY(p, hipMemcpyAsync(&cs, dsum, sizeof(cs), hipMemcpyDeviceToHost, s));
+        HIP_TRY(p, hipStreamSynchronize(s));
+        if ((int64_t)cs.total != p->nnz) {
+            p->err = "column-block counts do not add up to nnz";
+            return SPMV_E_HIP;
+        }
+        p->ccp = ccp; p->irow_t = irow_t; p->val_t = val_t; p->has_ccs = true;
+        p->st.max_col = cs.max_len;
+        p->jcol = nullptr; p->has_coo_col = false;
+        p->ellc_w = -1; p->ellc_val = nullptr; p->ellc_row = nullptr;
+        return SPMV_OK;
+    }
+
     int32_t* cursor = reinterpret_cast<int32_t*>(base + w.cursor);
     int32_t* bsum = reinterpret_cast<int32_t*>(base + w.bsum);
     int32_t* mid = reinterpret_cast<int32_t*>(base + w.mid);
     int32_t* lng = reinterpret_cast<int32_t*>(base + w.lng);
-    ColSummary* dsum = reinterpret_cast<ColSummary*>(base + w.sum);
     unsigned long long* keys = reinterpret_cast<unsigned long long*>(base + w.keys);
     unsigned long long* tmp = reinterpret_cast<unsigned long long*>(base + w.tmp);
-    int32_t* ccp = static_cast<int32_t*>(out->ptr[0]);
-    int32_t* irow_t = static_cast<int32_t*>(out->ptr[1]);
-    void* val_t = out->ptr[2];
-    const int vb = vbytes_of(p->dt);
 
     // (1) column counts, (2) exclusive scan -> ccp and cursors
     HIP_TRY(p, hipMemsetAsync(cursor, 0, (size_t)p->n * 4, s));
     if (p->nnz > 0) HIP_TRY(p, launch_col_count(p->n, p->irp, p->icol, cursor, s));
     HIP_TRY(p, launch_col_scan(p->n, cursor, ccp, cursor, bsum, mid, lng, dsum, s));
-    ColSummary cs{};
     HIP_TRY(p, hipMemcpyAsync(&cs, dsum, sizeof(cs), hipMemcpyDeviceToHost, s));
     HIP_TRY(p, hipStreamSynchronize(s));
     if ((int64_t)cs.total != p->nnz) {
@@ -412,9 +452,10 @@ SPMV_API spmv_status at_table_build(const double* d, const double* r, const int3
 namespace {
 
 int dbucket(double d) {
-    if (!(d >= 0)) return 0;
-    int b = (int)std::floor(d / 0.5);
-    return b < 0 ? 0 : (b >= AT_DBUCKETS ? AT_DBUCKETS - 1 : b);
+    static const double edges[AT_DBUCKETS - 1] = {0.0625, 0.125, 0.25, 0.5, 1.0, 2.0, 4.0};
+    int b = 0;
+    while (b < AT_DBUCKETS - 1 && d >= edges[b]) ++b;
+    return b;
 }
 
 // Algorithmic bytes of one SpMV in a format (x and y counted once, ELL
@@ -462,12 +503,13 @@ SPMV_API spmv_status at_choose_format_stats(const spmv_stats* st, spmv_dtype dt,
         // least estimated transformation + k SpMVs; ties keep CRS
         d.rule = 1;
         const int b = dbucket(st->d_mat);
+        const int loc = st->bandwidth <= AT_LOCAL_BAND ? 0 : 1;
         const double k = (double)k_repeats;
         auto est = [&](double bytes, double bps, int launches) {
             return bps > 0 ? bytes / bps + launches * t->launch_s : std::numeric_limits<double>::infinity();
         };
-        const double tc0 = est(spmv_bytes(*st, dt, SPMV_CRS), t->spmv_bps[SPMV_CRS][0][b], 1);
-        const double tc1 = est(spmv_bytes(*st, dt, SPMV_CRS), t->spmv_bps[SPMV_CRS][1][b], 1);
+        const double tc0 = est(spmv_bytes(*st, dt, SPMV_CRS), t->spmv_bps[loc][SPMV_CRS][0][b], 1);
+        const double tc1 = est(spmv_bytes(*st, dt, SPMV_CRS), t->spmv_bps[loc][SPMV_CRS][1][b], 1);
         spmv_format bf = SPMV_CRS;
         int bv = tc1 < tc0 ? 1 : 0;
         const double tcrs = std::min(tc0, tc1);
@@ -475,8 +517,8 @@ SPMV_API spmv_status at_choose_format_stats(const spmv_stats* st, spmv_dtype dt,
         const spmv_format cands[2] = {SPMV_COO_ROW, SPMV_ELL_ROW};
         for (spmv_format f : cands) {
             if (f == SPMV_ELL_ROW && !d.feasible_ell) continue;
-            const double ts = est(spmv_bytes(*st, dt, f), t->spmv_bps[f][0][b], f == SPMV_COO_ROW ? 2 : 1);
-            const double tr = est(trans_bytes(*st, dt, f), t->trans_bps[f][b], 1);
+            const double ts = est(spmv_bytes(*st, dt, f), t->spmv_bps[loc][f][0][b], f == SPMV_COO_ROW ? 2 : 1);
+            const double tr = est(trans_bytes(*st, dt, f), t->trans_bps[loc][f][b], 1);
             const double cost = tr + k * ts;
             if (cost < best) { best = cost; bf = f; bv = 0; bt = ts; btr = tr; }
         }

@@ -1,7 +1,9 @@
 """Off-line phase of the auto-tuner (section 2.2), run once per machine.
 
 For each benchmark matrix (the row-length sweep: n = 1,048,576, mean 32
-entries per row, D_mat = 0, 0.125, ..., 4) it measures on the GPU the CRS
+entries per row, D_mat = 0, 0.125, ..., 4, in two column families: uniform
+over the whole row ("scattered") and uniform within 4096 of the diagonal
+("local")) it measures on the GPU the CRS
 SpMV time t_crs, the ELL-Row SpMV time t_ell and the CRS -> ELL-Row
 transformation time t_trans, and computes SP = t_crs / t_ell (Eq. (1)),
 TT = t_trans / t_crs (Eq. (2), as the transformation cost in CRS-SpMV units),
@@ -10,7 +12,8 @@ whose R_ell falls below c = 1 (at_table_build); points where ELL does not
 fit the memory limit are recorded as infeasible and left out, as the paper
 did for torso1.  The same timings calibrate the cost model used by the
 amortised (k-aware) decision: algorithmic bytes per second of each format,
-variant and transformation per D_mat bucket.
+variant and transformation per locality class (bandwidth <= 65536 or not)
+and D_mat bucket.
 
     python -m paper_2407_00019_amd.offline [--points 0,4,8] [--out FILE]
 
@@ -83,7 +86,7 @@ def measure_point(m, dtype, x, reps=7):
     n, nnz = m.n, m.nnz
     vb, xb = val.element_size(), xd.element_size()
     y = torch.empty_like(xd)
-    out = {"n": n, "nnz": nnz, "d_mat": st.d_mat, "width": st.max_row, "dtype": dtype}
+    out = {"n": n, "nnz": nnz, "d_mat": st.d_mat, "width": st.max_row, "bandwidth": st.bandwidth, "dtype": dtype}
     out["t_crs_scalar"] = time_call(lambda: plan.spmv(spmvat.CRS, xd, y, 0), reps)
     out["t_crs_best"] = time_call(lambda: plan.spmv(spmvat.CRS, xd, y, 1), reps)
     coo_buf = plan._alloc(spmvat.COO_ROW)[0]
@@ -136,7 +139,12 @@ def launch_overhead_s():
 
 
 def bucket(d):
-    return min(spmvat.AT_DBUCKETS - 1, max(0, int(math.floor(d / 0.5))))
+    """D_mat bucket: how many of the edges 1/16, 1/8, ..., 4 D_mat reaches."""
+    return sum(1 for e in spmvat.AT_DBUCKET_EDGES if d >= e)
+
+
+def locality(bw):
+    return 0 if bw <= spmvat.AT_LOCAL_BAND else 1
 
 
 def main(argv=None):
@@ -147,15 +155,16 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=7)
     ap.add_argument("--out", default=os.path.join(_HERE, "at_table.json"))
     ap.add_argument("--c", type=float, default=1.0)
+    ap.add_argument("--families", default="scattered,local")
     a = ap.parse_args(argv)
     idx = list(range(len(gen.DSWEEP_TARGETS))) if a.points == "all" else [int(s) for s in a.points.split(",")]
     dts = {"f64": spmvat.F64, "f32": spmvat.F32, "bf16": spmvat.BF16, "f16": spmvat.F16}
     dlist = [dts[s] for s in a.dtypes.split(",")]
     launch_s = launch_overhead_s()
     points = []
-    for i in idx:
+    for fam, i in [(f, i) for f in a.families.split(",") for i in idx]:
         t0 = time.time()
-        m = gen.dsweep_matrix(i)
+        m = gen.dsweep_matrix(i, local=(fam == "local"))
         x = torch.from_numpy(gen.x_uniform(m.n, gen.seed_for(5, 100 + i)))
         res = {}
         for dt in dlist:
@@ -163,7 +172,7 @@ def main(argv=None):
             p.update(derive(p))
             res[dt] = p
         y64 = res[spmvat.F64]["y"] if spmvat.F64 in res else None
-        rec = {"index": i, "d_target": gen.DSWEEP_TARGETS[i], "gen_s": round(time.time() - t0, 2)}
+        rec = {"family": fam, "index": i, "d_target": gen.DSWEEP_TARGETS[i], "gen_s": round(time.time() - t0, 2)}
         for dt, p in res.items():
             name = [k for k, v in dts.items() if v == dt][0]
             q = {k: v for k, v in p.items() if k not in ("y",)}
@@ -174,29 +183,34 @@ def main(argv=None):
         print(json.dumps({k: (v if not isinstance(v, dict) else {kk: vv for kk, vv in v.items() if kk != "bytes"})
                           for k, v in rec.items()}), flush=True)
 
-    # the D_mat - R_ell graph in binary64 and D*, against both CRS kernels
+    # the D_mat - R_ell graph in binary64 and D*, against both CRS kernels,
+    # per family and over all benchmark points together
     f64 = [p["f64"] for p in points if "f64" in p]
+    fams = [p["family"] for p in points if "f64" in p]
     table = {"c": a.c, "machine": torch.cuda.get_device_name(0), "points": len(f64)}
     for base in ("scalar", "best"):
-        d = [q["d_mat"] for q in f64]
-        r = [q[f"r_ell_{base}"] if q["ell_feasible"] else 0.0 for q in f64]
-        feas = [1 if q["ell_feasible"] else 0 for q in f64]
-        t = spmvat.at_table_build(d, r, feas, a.c)
-        table[f"d_star_vs_{base}"] = t.d_star if math.isfinite(t.d_star) else "inf"
-        table[f"graph_vs_{base}"] = [[dd, rr, ff] for dd, rr, ff in zip(d, r, feas)]
-    # the on-line paper rule falls back to the library's best CRS kernel, so
-    # D* is taken against it
+        for fam in sorted(set(fams)) + ["all"]:
+            sel = [q for q, f in zip(f64, fams) if fam == "all" or f == fam]
+            d = [q["d_mat"] for q in sel]
+            r = [q[f"r_ell_{base}"] if q["ell_feasible"] else 0.0 for q in sel]
+            feas = [1 if q["ell_feasible"] else 0 for q in sel]
+            t = spmvat.at_table_build(d, r, feas, a.c)
+            table[f"d_star_vs_{base}_{fam}"] = t.d_star if math.isfinite(t.d_star) else "inf"
+            if fam != "all":
+                table[f"graph_vs_{base}_{fam}"] = [[dd, rr, ff] for dd, rr, ff in zip(d, r, feas)]
+    # the on-line paper rule falls back to the library's CRS kernel, so D* is
+    # taken against it, over every benchmark point
     table["d"] = [q["d_mat"] for q in f64]
     table["r"] = [q["r_ell_best"] if q["ell_feasible"] else 0.0 for q in f64]
     table["feasible"] = [1 if q["ell_feasible"] else 0 for q in f64]
-    # cost model: mean algorithmic bytes/s per format, variant and D bucket
-    spmv_bps = {str(spmvat.CRS): [[0.0] * spmvat.AT_DBUCKETS, [0.0] * spmvat.AT_DBUCKETS],
-                str(spmvat.COO_ROW): [[0.0] * spmvat.AT_DBUCKETS, [0.0] * spmvat.AT_DBUCKETS],
-                str(spmvat.ELL_ROW): [[0.0] * spmvat.AT_DBUCKETS, [0.0] * spmvat.AT_DBUCKETS]}
-    trans_bps = {str(spmvat.COO_ROW): [0.0] * spmvat.AT_DBUCKETS, str(spmvat.ELL_ROW): [0.0] * spmvat.AT_DBUCKETS}
+    # cost model: mean algorithmic bytes/s per locality, format, variant, D bucket
+    nb = spmvat.AT_DBUCKETS
+    spmv_bps = [{str(f): [[0.0] * nb, [0.0] * nb] for f in (spmvat.CRS, spmvat.COO_ROW, spmvat.ELL_ROW)}
+                for _ in range(2)]
+    trans_bps = [{str(f): [0.0] * nb for f in (spmvat.COO_ROW, spmvat.ELL_ROW)} for _ in range(2)]
     acc = {}
     for q in f64:
-        b = bucket(q["d_mat"])
+        b, loc = bucket(q["d_mat"]), locality(q["bandwidth"])
         B = q["bytes"]
         obs = [((spmvat.CRS, 0), B["crs"] / (q["t_crs_scalar"] * 1e-3 - launch_s)),
                ((spmvat.CRS, 1), B["crs"] / (q["t_crs_best"] * 1e-3 - launch_s)),
@@ -206,31 +220,44 @@ def main(argv=None):
             obs += [((spmvat.ELL_ROW, 0), B["ell_row"] / (q["t_ell"] * 1e-3 - launch_s)),
                     (("t", spmvat.ELL_ROW), B["trans_ell"] / (q["t_trans_ell"] * 1e-3 - launch_s))]
         for key, v in obs:
-            acc.setdefault((key, b), []).append(max(v, 1.0))
-    for (key, b), vals in acc.items():
+            acc.setdefault((loc, key, b), []).append(max(v, 1.0))
+    for (loc, key, b), vals in acc.items():
         v = statistics.mean(vals)
         if key[0] == "t":
-            trans_bps[str(key[1])][b] = v
+            trans_bps[loc][str(key[1])][b] = v
         else:
-            spmv_bps[str(key[0])][key[1]][b] = v
-    # buckets without a sample take the nearest sampled bucket below (or above)
+            spmv_bps[loc][str(key[0])][key[1]][b] = v
+
+    # buckets without a sample take the nearest sampled bucket below (else
+    # above); a class without any sample for an entry takes the other class's
     def fill(arr):
         for k in range(len(arr)):
             if arr[k] == 0.0:
                 lower = [arr[j] for j in range(k - 1, -1, -1) if arr[j] > 0]
                 upper = [arr[j] for j in range(k + 1, len(arr)) if arr[j] > 0]
                 arr[k] = lower[0] if lower else (upper[0] if upper else 0.0)
-    for f in spmv_bps.values():
-        for v in f:
+    for loc in range(2):
+        for f in spmv_bps[loc].values():
+            for v in f:
+                fill(v)
+        for v in trans_bps[loc].values():
             fill(v)
-    for v in trans_bps.values():
-        fill(v)
-    table["cost_model"] = {"spmv_bps": spmv_bps, "trans_bps": trans_bps, "launch_s": launch_s}
+    for loc in range(2):
+        other = 1 - loc
+        for f, per_v in spmv_bps[loc].items():
+            for v_ in range(2):
+                if not any(per_v[v_]):
+                    per_v[v_] = list(spmv_bps[other][f][v_])
+        for f, arr in trans_bps[loc].items():
+            if not any(arr):
+                trans_bps[loc][f] = list(trans_bps[other][f])
+    table["cost_model"] = {"spmv_bps": spmv_bps, "trans_bps": trans_bps, "launch_s": launch_s,
+                           "local_band": spmvat.AT_LOCAL_BAND, "d_edges": list(spmvat.AT_DBUCKET_EDGES)}
     table["sweep"] = points
     with open(a.out, "w") as f:
         json.dump(table, f, indent=1, default=float)
-    print(json.dumps({"d_star_vs_scalar": table["d_star_vs_scalar"], "d_star_vs_best": table["d_star_vs_best"],
-                      "launch_us": launch_s * 1e6, "out": a.out}), flush=True)
+    print(json.dumps({k: v for k, v in table.items() if k.startswith("d_star")} |
+                     {"launch_us": launch_s * 1e6, "out": a.out}), flush=True)
 
 
 if __name__ == "__main__":

@@ -88,20 +88,7 @@ def load_table() -> spmvat.at_table:
     if not os.path.exists(path):
         return spmvat.at_table_build([], [], None, 1.0)
     with open(path) as f:
-        d = json.load(f)
-    t = spmvat.at_table_build(d["d"], d["r"], d["feasible"], d.get("c", 1.0))
-    cm = d.get("cost_model")
-    if cm:
-        t.calibrated = 1
-        for f_, per_v in cm["spmv_bps"].items():
-            for v_, buckets in enumerate(per_v):
-                for b_, val in enumerate(buckets):
-                    t.spmv_bps[int(f_)][v_][b_] = val
-        for f_, buckets in cm["trans_bps"].items():
-            for b_, val in enumerate(buckets):
-                t.trans_bps[int(f_)][b_] = val
-        t.launch_s = cm.get("launch_s", 0.0)
-    return t
+        return spmvat.at_table_from_json(json.load(f))
 
 
 def run(jobs, policy: int, slots: int = 8, hbm_cap: int = 200 << 30, table=None, arrivals=None,

@@ -68,10 +68,11 @@ def test_dstar_matches_oracle(seed):
     assert t.c == 1.0
 
 
-def _stats(n, nnz, max_row, d_mat):
+def _stats(n, nnz, max_row, d_mat, bandwidth=100):
     spmvat = _lib()
     st = spmvat.spmv_stats()
     st.n, st.nnz, st.max_row, st.min_row, st.max_col = n, nnz, max_row, 1, -1
+    st.bandwidth = bandwidth
     st.sum_len = nnz
     st.mu = nnz / n
     st.d_mat = d_mat
@@ -94,16 +95,17 @@ def test_paper_rule_and_memory_guard():
     assert spmvat.at_choose_format_stats(st, spmvat.F64, 27 * 1000 * 12, t, 0)[0] == spmvat.ELL_ROW
 
 
-def _calibrated(spmvat, crs0, crs1, coo, ell, tr_coo, tr_ell, launch=0.0):
+def _calibrated(spmvat, crs0, crs1, coo, ell, tr_coo, tr_ell, launch=0.0, loc=(0, 1), buckets=None):
     t = spmvat.at_table_build([], [], None, 1.0)
     t.calibrated = 1
-    for b in range(spmvat.AT_DBUCKETS):
-        t.spmv_bps[spmvat.CRS][0][b] = crs0
-        t.spmv_bps[spmvat.CRS][1][b] = crs1
-        t.spmv_bps[spmvat.COO_ROW][0][b] = coo
-        t.spmv_bps[spmvat.ELL_ROW][0][b] = ell
-        t.trans_bps[spmvat.COO_ROW][b] = tr_coo
-        t.trans_bps[spmvat.ELL_ROW][b] = tr_ell
+    for l in loc:
+        for b in (range(spmvat.AT_DBUCKETS) if buckets is None else buckets):
+            t.spmv_bps[l][spmvat.CRS][0][b] = crs0
+            t.spmv_bps[l][spmvat.CRS][1][b] = crs1
+            t.spmv_bps[l][spmvat.COO_ROW][0][b] = coo
+            t.spmv_bps[l][spmvat.ELL_ROW][0][b] = ell
+            t.trans_bps[l][spmvat.COO_ROW][b] = tr_coo
+            t.trans_bps[l][spmvat.ELL_ROW][b] = tr_ell
     t.launch_s = launch
     return t
 
@@ -137,6 +139,26 @@ def test_k_aware_choice_matches_oracle(k, dtype):
     else:
         ts = cands[got][1]
         assert why.k_break_even == pytest.approx((cands[got][0] / tcrs) / (1 - ts / tcrs))
+
+
+def test_cost_model_cell_follows_locality_and_d_bucket():
+    """The k-aware choice reads the table cell of the matrix's locality class
+    (bandwidth <= 65536 or not) and D_mat bucket (edges 1/16, 1/8, 1/4, 1/2,
+    1, 2, 4): an ELL rate present in only one cell wins only there."""
+    spmvat = _lib()
+    edges = spmvat.AT_DBUCKET_EDGES
+    for loc in (0, 1):
+        for b in range(spmvat.AT_DBUCKETS):
+            t = _calibrated(spmvat, 1e12, 1e12, 1e9, 0.0, 1e9, 0.0)
+            t.spmv_bps[loc][spmvat.ELL_ROW][0][b] = 1e13
+            t.trans_bps[loc][spmvat.ELL_ROW][b] = 1e13
+            for l2 in (0, 1):
+                for b2 in range(spmvat.AT_DBUCKETS):
+                    d = 0.0 if b2 == 0 else edges[b2 - 1]
+                    bw = spmvat.AT_LOCAL_BAND if l2 == 0 else spmvat.AT_LOCAL_BAND + 1
+                    st = _stats(100000, 2_600_000, 27, d, bandwidth=bw)
+                    f, v, why = spmvat.at_choose_format_stats(st, 0, 1 << 40, t, 100)
+                    assert (f == spmvat.ELL_ROW) == (l2 == loc and b2 == b), (loc, b, l2, b2)
 
 
 def test_uncalibrated_table_falls_back_to_paper_rule():

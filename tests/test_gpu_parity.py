@@ -100,6 +100,7 @@ def check_stats(m, st):
     s1, s2, mx, mn = oracle.row_moments(m.n, m.irp)
     mu, sg, d = oracle.dmat_from_moments(m.n, s1, s2)
     assert (st.sum_len, st.sum_len2, st.max_row, st.min_row) == (s1, s2, mx, mn)
+    assert st.bandwidth == oracle.bandwidth(m.n, m.irp, m.icol)
     assert bits(np.array([st.mu, st.sigma, st.d_mat])).tolist() == bits(np.array([mu, sg, d])).tolist()
 
 
@@ -213,6 +214,47 @@ def test_powerlaw_full_size():
                      (spmvat.COO_COL, 0), (spmvat.ELL_COL, 0)]:
         y = host(plan.spmv(fmt, xd, variant=var))
         assert oracle.rel_l2(y, yref) <= TOL64, (fmt, var)
+    plan.close()
+
+
+def banded_with_long_column(n, seed):
+    """Band of half-width 2 plus column 0 in every 8th row from row 8 on:
+    column 0 then holds those rows and rows 0-2 of the band."""
+    m = gen.banded(n, 2, seed)
+    rows = np.arange(8, n, 8)
+    at = m.irp[rows]
+    icol = np.insert(m.icol, at, 0)
+    val = np.insert(m.val, at, np.random.default_rng(seed).standard_normal(rows.shape[0]))
+    extra = np.zeros(n + 1, np.int64)
+    extra[rows + 1] = 1
+    irp = (m.irp + np.cumsum(extra)).astype(np.int32)
+    return gen.Crs(n, irp, icol.astype(np.int32), val, f"banded_long_n{n}")
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("n", [1 << 22, (1 << 22) + 3001])
+def test_ccs_on_both_sides_of_the_bucketed_limit(n):
+    """Up to n = 2^22 the CCS is built by the two-level counting sort (rows
+    packed in 22 bits); above it by the column counts and per-column sorts.
+    Both give the oracle's arrays bit for bit, long column included."""
+    import torch
+    spmvat = lib_ready()
+    m = banded_with_long_column(n, 31)
+    assert oracle.validate_crs(m.n, m.irp, m.icol) == 0
+    x = gen.x_uniform(m.n, 5)
+    irp, icol, val = to_dev(m)
+    plan = spmvat.Plan(irp, icol, val)
+    ccp, irow_t, val_t = plan.to_ccs()
+    (jcol,) = plan.to_coo(column_wise=True)
+    o_ccp, o_irow_t, o_val_t = oracle.csr_to_ccs(m.n, m.irp, m.icol, m.val)
+    assert plan.stats.max_col == int(np.diff(o_ccp).max()) == len(range(8, n, 8)) + 3
+    assert np.array_equal(host(ccp), o_ccp)
+    assert np.array_equal(host(irow_t), o_irow_t)
+    assert np.array_equal(bits(host(val_t)), bits(o_val_t))
+    assert np.array_equal(host(jcol), oracle.ccs_to_coo_col(m.n, o_ccp))
+    yref = oracle.spmv_crs(m.n, m.irp, m.icol, m.val, x)
+    y = host(plan.spmv(spmvat.COO_COL, torch.from_numpy(x).to("cuda:0")))
+    assert oracle.rel_l2(y, yref) <= TOL64
     plan.close()
 
 

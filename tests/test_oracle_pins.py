@@ -255,6 +255,35 @@ def test_dmat_constant_rows_and_empty():
     assert oracle.dmat(1, np.array([0, 3], np.int32)) == 0.0
 
 
+@pytest.mark.parametrize("case", SMALL_CASES)
+def test_bandwidth_is_max_distance_over_entries(case):
+    n, seed, ml, srt, dup, ef = case
+    m = gen.random_small(n, seed, ml, srt, dup, ef)
+    rows = np.repeat(np.arange(n), np.diff(m.irp))
+    want = int(np.abs(rows - m.icol).max()) if m.nnz else 0
+    assert oracle.bandwidth(n, m.irp, m.icol) == want
+
+
+def test_bandwidth_of_stencils_and_windows():
+    m = gen.laplace_64x64()
+    assert oracle.bandwidth(m.n, m.irp, m.icol) == 64
+    m = gen.stencil27(10, 10, 10, 1)
+    assert oracle.bandwidth(m.n, m.irp, m.icol) == 1 + 10 + 100
+    lens = np.full(5000, 7, np.int32)
+    m = gen.window_rows(5000, lens, 40, 3)
+    assert oracle.bandwidth(m.n, m.irp, m.icol) <= 40
+    # an arrow matrix (dense first row and column): bandwidth n - 1, whatever
+    # the order of the entries inside the rows
+    n = 300
+    rows = [[0] + list(range(n - 1, 0, -1))] + [[i, 0] for i in range(1, n)]
+    irp = np.cumsum([0] + [len(r) for r in rows]).astype(np.int32)
+    icol = np.concatenate([np.array(r, np.int32) for r in rows])
+    assert oracle.bandwidth(n, irp, icol) == n - 1
+    # a diagonal matrix has bandwidth 0, an empty one too
+    assert oracle.bandwidth(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32)) == 0
+    assert oracle.bandwidth(n, np.zeros(n + 1, np.int32), np.zeros(0, np.int32)) == 0
+
+
 def test_u128_rounding_matches_python():
     """Python's int -> float is correctly rounded (ties to even)."""
     rng = np.random.default_rng(5)
