@@ -233,10 +233,9 @@ def banded_with_long_column(n, seed):
 
 @pytest.mark.slow
 @pytest.mark.parametrize("n", [1 << 22, (1 << 22) + 3001])
-def test_ccs_on_both_sides_of_the_bucketed_limit(n):
-    """Up to n = 2^22 the CCS is built by the two-level counting sort (rows
-    packed in 22 bits); above it by the column counts and per-column sorts.
-    Both give the oracle's arrays bit for bit, long column included."""
+def test_ccs_with_a_long_column_at_large_n(n):
+    """n around 2^22 with one column of n / 8 entries (the multi-pass column
+    sort): the oracle's arrays bit for bit."""
     import torch
     spmvat = lib_ready()
     m = banded_with_long_column(n, 31)
