@@ -391,7 +391,7 @@ def serving(count):
     jobs = serve.build_jobs(gen.serving_jobs(count, rate_per_s=0.0))
     log(f"[bench] serving: built {count} jobs ({sum(j.nnz for j in jobs) / 1e6:.0f}M nonzeros) "
         f"in {time.time() - t0:.1f}s")
-    res = serve.compare(jobs, slots=8, hbm_cap=200 << 30, rate="auto", log=log)
+    res = serve.compare(jobs, slots=serve.DEFAULT_SLOTS, hbm_cap=200 << 30, rate="auto", log=log)
     res["jobs_of_stream"] = count
     res["nnz_total"] = int(sum(j.nnz for j in jobs))
     return res

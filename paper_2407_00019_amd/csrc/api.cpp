@@ -334,21 +334,21 @@ SPMV_API spmv_status csr_to_ell(spmv_plan* p, int column_wise, const spmv_buffer
 
 // ------------------------------------------------------------------ SpMV
 
-SPMV_API spmv_status spmv_exec(const spmv_plan* p, spmv_format f, int variant, const void* x, void* y,
-                               void* stream) {
+spmv_status spmvat::plan_exec(const spmv_plan* p, spmv_format f, int variant, const void* x, void* y,
+                              double alpha, hipStream_t s) {
     if (!p || !x || !y || !aligned16(x) || !aligned16(y)) return SPMV_E_ARG;
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (alpha != 1.0 && f != SPMV_CRS && f != SPMV_ELL_ROW) return SPMV_E_ARG;
     const int dt = (int)p->dt;
     const int64_t ybytes = (int64_t)p->n * xbytes_of(p->dt);
     switch (f) {
         case SPMV_CRS: {
             if (variant < 0 || variant > 8) return SPMV_E_ARG;
             const bool stream = variant == 8 || variant == 1;
-            if (variant == 0) HIP_TRY(p, launch_spmv_crs_scalar(dt, p->n, p->irp, p->icol, p->val, x, y, s));
-            else if (stream) HIP_TRY(p, launch_spmv_crs_stream(dt, p->n, p->irp, p->icol, p->val, x, y, s));
+            if (variant == 0) HIP_TRY(p, launch_spmv_crs_scalar(dt, p->n, p->irp, p->icol, p->val, x, y, alpha, s));
+            else if (stream) HIP_TRY(p, launch_spmv_crs_stream(dt, p->n, p->irp, p->icol, p->val, x, y, alpha, s));
             else {
                 const int w = 1 << (variant - 1);
-                HIP_TRY(p, launch_spmv_crs_vector(dt, w, p->n, p->irp, p->icol, p->val, x, y, s));
+                HIP_TRY(p, launch_spmv_crs_vector(dt, w, p->n, p->irp, p->icol, p->val, x, y, alpha, s));
             }
             return SPMV_OK;
         }
@@ -361,7 +361,7 @@ SPMV_API spmv_status spmv_exec(const spmv_plan* p, spmv_format f, int variant, c
         case SPMV_ELL_ROW:
             if (variant != 0) return SPMV_E_ARG;
             if (p->ell_w < 0) return SPMV_E_NOT_READY;
-            HIP_TRY(p, launch_spmv_ell_row(dt, p->n, p->ell_w, p->ell_val, p->ell_col, x, y, s));
+            HIP_TRY(p, launch_spmv_ell_row(dt, p->n, p->ell_w, p->ell_val, p->ell_col, x, y, alpha, s));
             return SPMV_OK;
         case SPMV_ELL_COL:
             if (variant != 0) return SPMV_E_ARG;
@@ -380,6 +380,11 @@ SPMV_API spmv_status spmv_exec(const spmv_plan* p, spmv_format f, int variant, c
         default:
             return SPMV_E_ARG;
     }
+}
+
+SPMV_API spmv_status spmv_exec(const spmv_plan* p, spmv_format f, int variant, const void* x, void* y,
+                               void* stream) {
+    return plan_exec(p, f, variant, x, y, 1.0, static_cast<hipStream_t>(stream));
 }
 
 // ----------------------------------------------------------- conversion

@@ -32,19 +32,19 @@ __device__ __forceinline__ void atomic_add(X* p, X v) { unsafeAtomicAdd(p, v); }
 template <typename V, typename X>
 __global__ void __launch_bounds__(kBlock)
 k_spmv_crs_scalar(int n, const int* __restrict__ irp, const int* __restrict__ icol, const V* __restrict__ val,
-                  const X* __restrict__ x, X* __restrict__ y) {
+                  const X* __restrict__ x, X* __restrict__ y, X alpha) {
     const int i = (int)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= n) return;
     const int a = irp[i], b = irp[i + 1];
     X s = 0;
     for (int p = a; p < b; ++p) s += (X)widen(val[p]) * x[icol[p]];
-    y[i] = s;
+    y[i] = s * alpha;
 }
 
 template <typename V, typename X, int W>
 __global__ void __launch_bounds__(kBlock)
 k_spmv_crs_vector(int n, const int* __restrict__ irp, const int* __restrict__ icol, const V* __restrict__ val,
-                  const X* __restrict__ x, X* __restrict__ y) {
+                  const X* __restrict__ x, X* __restrict__ y, X alpha) {
     constexpr int kRows = kBlock / W;
     const int row = (int)xcd_block(blockIdx.x, gridDim.x) * kRows + (int)threadIdx.x / W;
     const int lane = threadIdx.x % W;
@@ -55,7 +55,7 @@ k_spmv_crs_vector(int n, const int* __restrict__ irp, const int* __restrict__ ic
     }
 #pragma unroll
     for (int off = W / 2; off > 0; off >>= 1) s += __shfl_down(s, off, W);
-    if (lane == 0 && row < n) y[row] = s;
+    if (lane == 0 && row < n) y[row] = s * alpha;
 }
 
 constexpr int kStreamCap = 2048;   // products staged in LDS per chunk
@@ -64,7 +64,7 @@ constexpr int kStreamLong = 256;   // rows longer than this are summed by the wh
 template <typename V, typename X>
 __global__ void __launch_bounds__(kBlock)
 k_spmv_crs_stream(int n, const int* __restrict__ irp, const int* __restrict__ icol, const V* __restrict__ val,
-                  const X* __restrict__ x, X* __restrict__ y) {
+                  const X* __restrict__ x, X* __restrict__ y, X alpha) {
     __shared__ X prod[kStreamCap];
     __shared__ int sp[kBlock + 1];
     __shared__ unsigned long long s_long[kBlock / kWave];
@@ -121,7 +121,7 @@ k_spmv_crs_stream(int n, const int* __restrict__ irp, const int* __restrict__ ic
         }
         __syncthreads();
     }
-    if (t < rows) y[r0 + t] = s;
+    if (t < rows) y[r0 + t] = s * alpha;
 }
 
 // ------------------------------------------------------------- ELL
@@ -129,7 +129,7 @@ k_spmv_crs_stream(int n, const int* __restrict__ irp, const int* __restrict__ ic
 template <typename V, typename X>
 __global__ void __launch_bounds__(kBlock)
 k_spmv_ell_row(int n, int width, const V* __restrict__ ev, const int* __restrict__ ec, const X* __restrict__ x,
-               X* __restrict__ y) {
+               X* __restrict__ y, X alpha) {
     const int i = (int)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= n) return;
     X s = 0;
@@ -137,7 +137,7 @@ k_spmv_ell_row(int n, int width, const V* __restrict__ ev, const int* __restrict
 #pragma unroll 8
     for (int k = 0; k < width; ++k, off += (size_t)n)
         s += (X)widen(ld_nt(&ev[off])) * x[ld_nt(&ec[off])];
-    y[i] = s;
+    y[i] = s * alpha;
 }
 
 // Two consecutive rows per thread: one 2-element load per slot for values
@@ -145,7 +145,7 @@ k_spmv_ell_row(int n, int width, const V* __restrict__ ev, const int* __restrict
 template <typename V, typename X>
 __global__ void __launch_bounds__(kBlock)
 k_spmv_ell_row2(int n, int width, const V* __restrict__ ev, const int* __restrict__ ec, const X* __restrict__ x,
-                X* __restrict__ y) {
+                X* __restrict__ y, X alpha) {
     const int i = ((int)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) * 2;
     if (i >= n) return;
     X s0 = 0, s1 = 0;
@@ -159,8 +159,8 @@ k_spmv_ell_row2(int n, int width, const V* __restrict__ ev, const int* __restric
         s0 += (X)widen(v0) * x[c0];
         s1 += (X)widen(v1) * x[c1];
     }
-    y[i] = s0;
-    y[i + 1] = s1;
+    y[i] = s0 * alpha;
+    y[i + 1] = s1 * alpha;
 }
 
 template <typename V, typename X>
@@ -422,24 +422,24 @@ static inline unsigned grid_for(int64_t items, int per_block) {
     }
 
 hipError_t launch_spmv_crs_stream(int dtype, int n, const int* irp, const int* icol, const void* val,
-                                  const void* x, void* y, hipStream_t s) {
+                                  const void* x, void* y, double alpha, hipStream_t s) {
     SPMV_DISPATCH(dtype, hipLaunchKernelGGL((k_spmv_crs_stream<V, X>), dim3(grid_for(n, kBlock)), dim3(kBlock),
-                                            0, s, n, irp, icol, (const V*)val, (const X*)x, (X*)y));
+                                            0, s, n, irp, icol, (const V*)val, (const X*)x, (X*)y, (X)alpha));
     return hipGetLastError();
 }
 
 hipError_t launch_spmv_crs_scalar(int dtype, int n, const int* irp, const int* icol, const void* val,
-                                  const void* x, void* y, hipStream_t s) {
+                                  const void* x, void* y, double alpha, hipStream_t s) {
     SPMV_DISPATCH(dtype, hipLaunchKernelGGL((k_spmv_crs_scalar<V, X>), dim3(grid_for(n, kBlock)), dim3(kBlock),
-                                            0, s, n, irp, icol, (const V*)val, (const X*)x, (X*)y));
+                                            0, s, n, irp, icol, (const V*)val, (const X*)x, (X*)y, (X)alpha));
     return hipGetLastError();
 }
 
 template <typename V, typename X>
 static void crs_vector_w(int width, int n, const int* irp, const int* icol, const void* val, const void* x,
-                         void* y, hipStream_t s) {
+                         void* y, double alpha, hipStream_t s) {
 #define CRSV(W) hipLaunchKernelGGL((k_spmv_crs_vector<V, X, W>), dim3(grid_for(n, kBlock / W)), dim3(kBlock), 0, s, \
-                                   n, irp, icol, (const V*)val, (const X*)x, (X*)y)
+                                   n, irp, icol, (const V*)val, (const X*)x, (X*)y, (X)alpha)
     switch (width) {
         case 2: CRSV(2); break;
         case 4: CRSV(4); break;
@@ -452,21 +452,21 @@ static void crs_vector_w(int width, int n, const int* irp, const int* icol, cons
 }
 
 hipError_t launch_spmv_crs_vector(int dtype, int width, int n, const int* irp, const int* icol, const void* val,
-                                  const void* x, void* y, hipStream_t s) {
-    SPMV_DISPATCH(dtype, (crs_vector_w<V, X>(width, n, irp, icol, val, x, y, s)));
+                                  const void* x, void* y, double alpha, hipStream_t s) {
+    SPMV_DISPATCH(dtype, (crs_vector_w<V, X>(width, n, irp, icol, val, x, y, alpha, s)));
     return hipGetLastError();
 }
 
 hipError_t launch_spmv_ell_row(int dtype, int n, int width, const void* ev, const int* ec, const void* x,
-                               void* y, hipStream_t s) {
+                               void* y, double alpha, hipStream_t s) {
     if (dtype == 0 && n % 2 == 0) {
         // binary64: two rows per thread measured faster; narrower values lose
         // parallelism without gaining wider loads, so they keep one row
         hipLaunchKernelGGL((k_spmv_ell_row2<double, double>), dim3(grid_for(n / 2, kBlock)), dim3(kBlock), 0, s, n,
-                           width, (const double*)ev, ec, (const double*)x, (double*)y);
+                           width, (const double*)ev, ec, (const double*)x, (double*)y, alpha);
     } else {
         SPMV_DISPATCH(dtype, hipLaunchKernelGGL((k_spmv_ell_row<V, X>), dim3(grid_for(n, kBlock)), dim3(kBlock), 0,
-                                                s, n, width, (const V*)ev, ec, (const X*)x, (X*)y));
+                                                s, n, width, (const V*)ev, ec, (const X*)x, (X*)y, (X)alpha));
     }
     return hipGetLastError();
 }

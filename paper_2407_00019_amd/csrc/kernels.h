@@ -58,18 +58,20 @@ hipError_t launch_ccs_sort_long(int start, int len, unsigned long long* keys, un
 hipError_t launch_ell_pack(int n, int width, const int* ptr, const int* idx, const void* val,
                            int vbytes, void* ell_val, int* ell_idx, hipStream_t s);
 
-// ---- SpMV (dtype: 0 F64, 1 F32, 2 BF16, 3 F16)
+// ---- SpMV (dtype: 0 F64, 1 F32, 2 BF16, 3 F16).  The CRS and ELL-Row
+// kernels store alpha * (A x)_i; spmv_exec passes alpha = 1, the server
+// passes the power-of-two scale of a job's chain (exact either way).
 hipError_t launch_fill_zero(void* y, int64_t bytes, hipStream_t s);
 // out = 2^-shift in (dtype 0: binary64, else binary32)
 hipError_t launch_scale_pow2(int dtype, int n, int shift, const void* in, void* out, hipStream_t s);
 hipError_t launch_spmv_crs_scalar(int dtype, int n, const int* irp, const int* icol, const void* val,
-                                  const void* x, void* y, hipStream_t s);
+                                  const void* x, void* y, double alpha, hipStream_t s);
 hipError_t launch_spmv_crs_stream(int dtype, int n, const int* irp, const int* icol, const void* val,
-                                  const void* x, void* y, hipStream_t s);
+                                  const void* x, void* y, double alpha, hipStream_t s);
 hipError_t launch_spmv_crs_vector(int dtype, int width, int n, const int* irp, const int* icol,
-                                  const void* val, const void* x, void* y, hipStream_t s);
+                                  const void* val, const void* x, void* y, double alpha, hipStream_t s);
 hipError_t launch_spmv_ell_row(int dtype, int n, int width, const void* ev, const int* ec,
-                               const void* x, void* y, hipStream_t s);
+                               const void* x, void* y, double alpha, hipStream_t s);
 hipError_t launch_spmv_ell_col(int dtype, int n, int width, const void* ev, const int* er,
                                const void* x, void* y, hipStream_t s);
 hipError_t launch_spmv_coo_row(int dtype, int n, int64_t nnz, const int* irow, const int* icol,

@@ -44,4 +44,9 @@ spmv_status plan_begin(spmv_plan* p, int32_t n, int64_t nnz, const int32_t* irp,
 // CRS contract is broken, else D_mat (Eq. (4)) and the memory limit.
 spmv_status plan_finish(spmv_plan* p, const RowStats& rs);
 
+// spmv_exec with the stored result scaled: y = alpha * A x.  alpha != 1 only
+// for CRS and ELL-Row (SPMV_E_ARG otherwise).
+spmv_status plan_exec(const spmv_plan* p, spmv_format f, int variant, const void* x, void* y, double alpha,
+                      hipStream_t s);
+
 }  // namespace spmvat

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -265,14 +266,30 @@ struct spmv_server {
         }
         s.res.format = (int32_t)f;
         s.res.variant = v;
+        // the chain x_{t+1} = 2^-shift A x_t, y_k = A x_k.  CRS and ELL-Row
+        // store the scaled product directly (one launch per step, x and y
+        // taking turns as input and output); COO-Row adds its carries after
+        // the main pass, so it keeps a separate scaling launch
+        const bool fused = f == SPMV_CRS || f == SPMV_ELL_ROW;
+        const double scale = std::ldexp(1.0, -s.job.shift);
+        float* in = s.x;
+        float* out = s.y;
         for (int32_t t = 0; t < s.job.k; ++t) {
-            st = spmv_exec(&s.plan, f, v, s.x, s.y, s.stream);
-            if (st == SPMV_OK && t + 1 < s.job.k &&
-                launch_scale_pow2(1, s.job.n, s.job.shift, s.y, s.x, s.stream) != hipSuccess)
-                st = SPMV_E_HIP;
+            const bool last = t + 1 == s.job.k;
+            if (fused) {
+                st = plan_exec(&s.plan, f, v, in, out, last ? 1.0 : scale, s.stream);
+                std::swap(in, out);
+            } else {
+                st = plan_exec(&s.plan, f, v, s.x, s.y, 1.0, s.stream);
+                if (st == SPMV_OK && !last &&
+                    launch_scale_pow2(1, s.job.n, s.job.shift, s.y, s.x, s.stream) != hipSuccess)
+                    st = SPMV_E_HIP;
+                in = s.y;
+            }
             if (st != SPMV_OK) { (void)hipStreamSynchronize(s.stream); finish(s, st); return; }
         }
-        hipError_t e = hipMemcpyAsync(s.job.y_out, s.y, 4 * (size_t)s.job.n, hipMemcpyDeviceToHost, s.stream);
+        // `in` holds y_k after the last step in either scheme
+        hipError_t e = hipMemcpyAsync(s.job.y_out, in, 4 * (size_t)s.job.n, hipMemcpyDeviceToHost, s.stream);
         if (e == hipSuccess) e = hipEventRecord(s.event, s.stream);
         if (e != hipSuccess) { (void)hipStreamSynchronize(s.stream); finish(s, SPMV_E_HIP); return; }
         s.state = SlotState::kRun;
