@@ -104,8 +104,9 @@ spmv_status plan_begin(spmv_plan* p, int32_t n, int64_t nnz, const int32_t* irp,
     p->n = n; p->nnz = nnz; p->dt = val_type;
     p->irp = irp; p->icol = icol; p->val = val;
     p->work = static_cast<char*>(plan_work); p->work_bytes = plan_work_bytes;
-    hipError_t e = launch_row_stats(n, nnz, irp, icol, plan_partials(p), plan_rowstats(p), s);
-    if (e == hipSuccess) e = hipMemcpyAsync(host_stats, plan_rowstats(p), sizeof(RowStats), hipMemcpyDeviceToHost, s);
+    // the final statistics kernel writes the result straight into the pinned
+    // host buffer: no copy command after it
+    const hipError_t e = launch_row_stats(n, nnz, irp, icol, plan_partials(p), plan_rowstats(p), host_stats, s);
     return e == hipSuccess ? SPMV_OK : hip_fail(p, e);
 }
 
@@ -152,10 +153,17 @@ SPMV_API spmv_status spmv_plan_create(spmv_plan** plan, int32_t n, int64_t nnz, 
     spmv_plan* p = new (std::nothrow) spmv_plan();
     if (!p) return SPMV_E_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    RowStats rs{};
-    spmv_status st = plan_begin(p, n, nnz, irp, icol, val, val_type, plan_work, plan_work_bytes, &rs, s);
+    // one pinned buffer per calling thread receives the statistics (kept
+    // for the life of the thread; plans on different threads do not share it)
+    thread_local RowStats* pinned = nullptr;
+    if (!pinned && hipHostMalloc(reinterpret_cast<void**>(&pinned), sizeof(RowStats), hipHostMallocCoherent) != hipSuccess) {
+        pinned = nullptr;
+        delete p;
+        return SPMV_E_HIP;
+    }
+    spmv_status st = plan_begin(p, n, nnz, irp, icol, val, val_type, plan_work, plan_work_bytes, pinned, s);
     if (st == SPMV_OK && hipStreamSynchronize(s) != hipSuccess) st = SPMV_E_HIP;
-    if (st == SPMV_OK) st = plan_finish(p, rs);
+    if (st == SPMV_OK) st = plan_finish(p, *pinned);
     if (st != SPMV_OK) { delete p; return st; }
     *plan = p;
     return SPMV_OK;

@@ -15,8 +15,8 @@
 
 namespace spmvat {
 
-constexpr int kStatsBlocks = 1024;   // workgroups of the first stage (partials in plan workspace)
-constexpr int kStatsCap = 8192;      // column indices staged per chunk
+constexpr int kStatsBlocks = 2048;   // workgroups of the first stage (partials in plan workspace)
+constexpr int kStatsCap = 4096;      // column indices staged per chunk (17 KiB of LDS: 6 workgroups per CU)
 
 // one pad word after every 32 staged indices: lanes walking runs of 32
 // entries then read 33 words apart, in distinct LDS banks
@@ -129,7 +129,8 @@ k_row_stats(int n, int64_t nnz, const int* __restrict__ irp, const int* __restri
 // Second stage: one workgroup folds the per-workgroup partials in a fixed
 // order (exact integers, so the order does not change the result anyway).
 __global__ void __launch_bounds__(kBlock)
-k_row_stats_final(int nparts, const RowStats* __restrict__ partial, RowStats* __restrict__ out) {
+k_row_stats_final(int nparts, const RowStats* __restrict__ partial, RowStats* __restrict__ out,
+                  RowStats* __restrict__ host_out) {
     __shared__ RowStats sh[kBlock / kWave];
     unsigned long long s1 = 0, s2 = 0;
     int mx = 0, band = 0;
@@ -161,18 +162,19 @@ k_row_stats_final(int nparts, const RowStats* __restrict__ partial, RowStats* __
             r.flags |= sh[k].flags; r.max_band = max(r.max_band, sh[k].max_band);
         }
         *out = r;
+        if (host_out) *host_out = r;   // pinned host memory: read after the stream synchronises
     }
 }
 
 size_t row_stats_partial_count() { return kStatsBlocks; }
 
 hipError_t launch_row_stats(int n, int64_t nnz, const int* irp, const int* icol, RowStats* partial,
-                            RowStats* out, hipStream_t s) {
+                            RowStats* out, RowStats* host_out, hipStream_t s) {
     int64_t blocks = ((int64_t)n + kBlock - 1) / kBlock;
     if (blocks > kStatsBlocks) blocks = kStatsBlocks;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_row_stats, dim3((unsigned)blocks), dim3(kBlock), 0, s, n, nnz, irp, icol, partial);
-    hipLaunchKernelGGL(k_row_stats_final, dim3(1), dim3(kBlock), 0, s, (int)blocks, partial, out);
+    hipLaunchKernelGGL(k_row_stats_final, dim3(1), dim3(kBlock), 0, s, (int)blocks, partial, out, host_out);
     return hipGetLastError();
 }
 

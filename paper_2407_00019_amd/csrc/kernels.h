@@ -35,8 +35,10 @@ constexpr int kCooTile = 256 * kCooPerThread;
 
 // ---- statistics
 size_t row_stats_partial_count();
+// The result goes to out (device) and, when host_out is not null, to that
+// pinned host address as well.
 hipError_t launch_row_stats(int n, int64_t nnz, const int* irp, const int* icol, RowStats* partial,
-                            RowStats* out, hipStream_t s);
+                            RowStats* out, RowStats* host_out, hipStream_t s);
 
 // ---- transformations
 hipError_t launch_expand_ptr(int n, const int* ptr, int* out, hipStream_t s);

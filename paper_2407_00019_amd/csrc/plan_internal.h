@@ -34,8 +34,8 @@ struct spmv_plan {
 namespace spmvat {
 
 // Validates the arguments of a plan, fills *p and enqueues the row
-// statistics on s, with their copy to *host_stats (pinned memory makes the
-// copy asynchronous).  No synchronisation.
+// statistics on s; their last kernel also writes them to *host_stats, which
+// must be pinned host memory (hipHostMalloc).  No synchronisation.
 spmv_status plan_begin(spmv_plan* p, int32_t n, int64_t nnz, const int32_t* irp, const int32_t* icol,
                        const void* val, spmv_dtype dt, void* work, size_t work_bytes, RowStats* host_stats,
                        hipStream_t s);

@@ -358,7 +358,7 @@ SPMV_API spmv_status spmv_server_create(const spmv_server_config* cfg, spmv_serv
     for (Slot& sl : s->slots) {
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&sl.event, hipEventDisableTiming) != hipSuccess ||
-            hipHostMalloc(reinterpret_cast<void**>(&sl.host_stats), sizeof(RowStats), hipHostMallocDefault) != hipSuccess) {
+            hipHostMalloc(reinterpret_cast<void**>(&sl.host_stats), sizeof(RowStats), hipHostMallocCoherent) != hipSuccess) {
             spmv_server_destroy(s);
             return SPMV_E_HIP;
         }
