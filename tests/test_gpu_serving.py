@@ -77,3 +77,54 @@ def test_too_large_job_is_reported_not_run():
     jobs = serve.build_jobs(small_specs(2, n_max=5000))
     res, _ = serve.run(jobs, 1, slots=2, hbm_cap=8192, arrivals=[0.0, 0.0])
     assert sorted(r.status for r in res) == [3, 3]
+
+
+@pytest.mark.slow
+def test_stream_prefix_at_full_size_sampled():
+    """The first 256 jobs of the serving stream at their real sizes (n up to
+    5e5) and chain lengths, in the configuration the benchmark replays
+    (default slots, 200 GB cap, burst arrivals), both policies.  Sampled jobs:
+    y_k alone equals y_k in the mix bit for bit, y_1 (the job rerun with
+    k = 1) is within relative L2 1e-5 of the binary64 oracle, and y_k is within
+    the binary32 chain bound of the oracle chain where that chain is cheap
+    enough to run on the CPU and stays in binary32's normal range (long
+    chains decay below it, and then the GPU's y_k must have underflowed)."""
+    import dataclasses
+    import torch
+    lib_ready()
+    from paper_2407_00019_amd import serve
+    jobs = serve.build_jobs(gen.serving_jobs(256, rate_per_s=0.0))
+    table = serve.load_table()
+    sample = sorted(set(list(range(0, 256, 23)) + [min(range(256), key=lambda i: jobs[i].k * jobs[i].nnz)]))
+    for policy in (0, 1):
+        res, _ = serve.run(jobs, policy, serve.DEFAULT_SLOTS, 200 << 30, table, [0.0] * len(jobs))
+        assert len(res) == len(jobs) and all(r.status == 0 for r in res)
+        fmt = {r.id: r.format for r in res}
+        mixed = {i: jobs[i].y.numpy().copy() for i in sample}
+        for i in sample:
+            j = jobs[i]
+            # a job alone needs far less than the stream's arena; the format
+            # decision takes min(the plan's limit, the largest free block),
+            # which is the plan's limit in both runs
+            r1, _ = serve.run([j], policy, 1, 16 << 30, table, [0.0])
+            assert r1[0].status == 0 and r1[0].format == fmt[j.id]
+            assert np.array_equal(j.y.numpy().view(np.uint32), mixed[i].view(np.uint32)), (policy, j.id)
+            one = dataclasses.replace(j, k=1, y=torch.empty(j.n, dtype=torch.float32, pin_memory=True))
+            r2, _ = serve.run([one], policy, 1, 16 << 30, table, [0.0])
+            assert r2[0].status == 0
+            y1 = oracle.spmv_crs(j.n, j.irp.numpy(), j.icol.numpy(), j.val.numpy().astype(np.float64),
+                                 j.x0.numpy().astype(np.float64))
+            assert oracle.rel_l2(one.y.numpy(), y1) <= 1e-5, (policy, j.id)
+            if j.k * j.nnz <= 3e8:
+                yref = oracle_chain(j)
+                if np.abs(yref).max() >= 2.0 ** -100:
+                    lmax = int(np.diff(j.irp.numpy()).max())
+                    u = 2.0 ** -24
+                    tol = j.k * (lmax + 1) * u / (1 - (lmax + 1) * u) * 4
+                    err = np.linalg.norm(mixed[i] - yref) / max(np.linalg.norm(yref), 1e-300)
+                    assert err <= max(tol, 1e-6), (policy, j.id, err, tol)
+                else:
+                    # the scaled chain decays below binary32's normal range
+                    # (the binary64 oracle keeps going): the GPU result has
+                    # underflowed too
+                    assert np.abs(mixed[i]).max() <= 2.0 ** -90, (policy, j.id)
