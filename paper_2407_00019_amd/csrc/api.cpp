@@ -280,7 +280,7 @@ SPMV_API spmv_status csr_to_ccs(spmv_plan* p, const spmv_buffers* out, void* wor
 
     // (1) column counts, (2) exclusive scan -> ccp and cursors
     HIP_TRY(p, hipMemsetAsync(cursor, 0, (size_t)p->n * 4, s));
-    if (p->nnz > 0) HIP_TRY(p, launch_col_count(p->n, p->irp, p->icol, cursor, s));
+    if (p->nnz > 0) HIP_TRY(p, launch_col_count(p->n, p->st.bandwidth, p->irp, p->icol, cursor, s));
     HIP_TRY(p, launch_col_scan(p->n, cursor, ccp, cursor, bsum, mid, lng, dsum, s));
     HIP_TRY(p, hipMemcpyAsync(&cs, dsum, sizeof(cs), hipMemcpyDeviceToHost, s));
     HIP_TRY(p, hipStreamSynchronize(s));

@@ -10,6 +10,8 @@
 //                 order (by row, then by position within the row), so every
 //                 output array is deterministic and bit-exact.
 //  * ELL pack     slot-major VAL(n, width) / index arrays with zero padding.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -121,7 +123,65 @@ k_col_walk(int n, const int* __restrict__ irp, const int* __restrict__ icol, int
     }
 }
 
-hipError_t launch_col_count(int n, const int* irp, const int* icol, int* cnt, hipStream_t s) {
+// Column counts with LDS privatisation, for matrices of small bandwidth bw
+// (max |i - j|): every column of rows [r0, r0 + R) lies in
+// [r0 - bw, r0 + R - 1 + bw], so a workgroup counts its rows' entries into
+// that window of bins in LDS (contiguous, coalesced reads of icol; LDS
+// atomics) and adds each non-zero bin to the global count with one atomic.
+// On the 27-point stencil a bin collects the 1-3 entries of one x-line, so
+// the global atomics drop threefold.  A column outside the window (only if
+// the CRS arrays changed after the plan was made) goes straight to the
+// global count.
+constexpr int kPrivBins = 36864;            // 144 KiB of LDS: one workgroup per CU
+constexpr int kPrivThreads = 1024;          // 16 waves hide the reads' latency
+constexpr int kPrivMinRows = 1024;          // below this many rows per window, use the walk
+
+__global__ void __launch_bounds__(kPrivThreads)
+k_col_count_priv(int n, int bw, int rows_per_tile, const int* __restrict__ irp, const int* __restrict__ icol,
+                 int* __restrict__ counter) {
+    __shared__ int bins[kPrivBins];
+    const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int r0 = tile * rows_per_tile;
+    const int r1 = min(n, r0 + rows_per_tile);
+    const int lo = max(0, r0 - bw);
+    const int hi = (int)min((int64_t)n, (int64_t)r1 + bw);
+    const int width = hi - lo;                  // <= rows_per_tile + 2 bw <= kPrivBins (host check)
+    for (int c = threadIdx.x; c < width; c += kPrivThreads) bins[c] = 0;
+    __syncthreads();
+    const int e0 = irp[r0], e1 = irp[r1];
+    constexpr int kUnroll = 4;
+    for (int base = e0; base < e1; base += kPrivThreads * kUnroll) {
+        // clamped, unconditional loads (base < e1): all in flight together
+        int c[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) c[u] = icol[min(base + u * kPrivThreads + (int)threadIdx.x, e1 - 1)];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (base + u * kPrivThreads + (int)threadIdx.x >= e1) continue;
+            const unsigned off = (unsigned)(c[u] - lo);
+            if (off < (unsigned)width) atomicAdd(&bins[off], 1);
+            else atomicAdd(&counter[c[u]], 1);
+        }
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < width; c += kPrivThreads) {
+        const int v = bins[c];
+        if (v) atomicAdd(&counter[lo + c], v);
+    }
+}
+
+hipError_t launch_col_count(int n, int bw, const int* irp, const int* icol, int* cnt, hipStream_t s) {
+    // privatised counts when a window of at least kPrivMinRows rows fits
+    int rows = 0;
+    if (bw >= 0 && (int64_t)2 * bw + kPrivMinRows <= kPrivBins) {
+        rows = std::min(8192, (int)((kPrivBins - 2 * (int64_t)bw) / kBlock * kBlock));
+        rows = std::min(rows, ((n + kBlock - 1) / kBlock) * kBlock);
+    }
+    if (rows >= kPrivMinRows || (rows > 0 && rows >= n)) {
+        const unsigned tiles = (unsigned)((n + rows - 1) / rows);
+        hipLaunchKernelGGL(k_col_count_priv, dim3(tiles), dim3(kPrivThreads), 0, s, n, bw, rows, irp, icol, cnt);
+        return hipGetLastError();
+    }
     unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_col_walk<false>, dim3(blocks), dim3(kBlock), 0, s, n, irp, icol, cnt, nullptr);
     return hipGetLastError();

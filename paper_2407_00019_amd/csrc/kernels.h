@@ -42,7 +42,9 @@ hipError_t launch_row_stats(int n, int64_t nnz, const int* irp, const int* icol,
 
 // ---- transformations
 hipError_t launch_expand_ptr(int n, const int* ptr, int* out, hipStream_t s);
-hipError_t launch_col_count(int n, const int* irp, const int* icol, int* cnt, hipStream_t s);
+// Column counts (added into cnt); bw = the matrix bandwidth from the row
+// statistics selects the LDS-privatised kernel when its window fits.
+hipError_t launch_col_count(int n, int bw, const int* irp, const int* icol, int* cnt, hipStream_t s);
 hipError_t launch_col_scan(int n, const int* cnt, int* ccp, int* cursor, int* bsum,
                            int* mid_list, int* long_list, ColSummary* sum, hipStream_t s);
 size_t col_scan_bsum_count(int n);   // per array; the scan needs two (sums, maxima)
