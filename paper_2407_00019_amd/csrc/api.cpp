@@ -290,7 +290,7 @@ SPMV_API spmv_status csr_to_ccs(spmv_plan* p, const spmv_buffers* out, void* wor
     }
     if (p->nnz > 0) {
         // (3) scatter of packed (position, row) keys, (4) per-column sort + emit
-        HIP_TRY(p, launch_ccs_scatter(p->n, p->irp, p->icol, cursor, keys, s));
+        HIP_TRY(p, launch_ccs_scatter(p->n, p->st.bandwidth, p->irp, p->icol, cursor, keys, s));
         HIP_TRY(p, launch_ccs_sort_small(p->n, ccp, keys, p->val, vb, irow_t, val_t, s));
         HIP_TRY(p, launch_ccs_sort_mid(cs.n_mid, mid, ccp, keys, p->val, vb, irow_t, val_t, s));
         if (cs.n_long > 0) {

@@ -300,8 +300,79 @@ hipError_t launch_col_scan(int n, const int* cnt, int* ccp, int* cursor, int* bs
 // through its cursor and stores the key (q << 32 | r) there.  Slot order
 // inside a column depends on scheduling; the sort below fixes it.
 
-hipError_t launch_ccs_scatter(int n, const int* irp, const int* icol, int* cursor, u64* keys,
+// The scatter with LDS privatisation (same window as the counts): a
+// workgroup counts its rows' entries per window column in LDS, reserves one
+// contiguous range of slots per touched column with a single global atomic,
+// then hands out slots inside those ranges with LDS atomics.  The row of an
+// entry comes from a binary search over the tile's row pointers in LDS.
+constexpr int kScatRows = 4096;                       // rows per tile at most
+constexpr int kScatBins = 40960 - (kScatRows + 1) - 63;   // just under the 160 KiB of LDS a workgroup may hold
+
+__global__ void __launch_bounds__(kPrivThreads)
+k_ccs_scatter_priv(int n, int bw, int rows_per_tile, const int* __restrict__ irp, const int* __restrict__ icol,
+                   int* __restrict__ cursor, u64* __restrict__ keys) {
+    __shared__ int bins[kScatBins];
+    __shared__ int sp[kScatRows + 1];
+    const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int r0 = tile * rows_per_tile;
+    const int rows = min(n, r0 + rows_per_tile) - r0;
+    const int lo = max(0, r0 - bw);
+    const int hi = (int)min((int64_t)n, (int64_t)r0 + rows + bw);
+    const int width = hi - lo;                  // <= rows_per_tile + 2 bw <= kScatBins (host check)
+    for (int c = threadIdx.x; c < width; c += kPrivThreads) bins[c] = 0;
+    for (int i = threadIdx.x; i <= rows; i += kPrivThreads) sp[i] = irp[r0 + i];
+    __syncthreads();
+    const int e0 = sp[0], e1 = sp[rows];
+    constexpr int kUnroll = 4;
+    // (1) entries per window column
+    for (int base = e0; base < e1; base += kPrivThreads * kUnroll) {
+        int c[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) c[u] = icol[min(base + u * kPrivThreads + (int)threadIdx.x, e1 - 1)];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (base + u * kPrivThreads + (int)threadIdx.x >= e1) continue;
+            const unsigned off = (unsigned)(c[u] - lo);
+            if (off < (unsigned)width) atomicAdd(&bins[off], 1);
+        }
+    }
+    __syncthreads();
+    // (2) one reservation per touched column; the bin becomes its cursor
+    for (int c = threadIdx.x; c < width; c += kPrivThreads) {
+        const int v = bins[c];
+        if (v) bins[c] = atomicAdd(&cursor[lo + c], v);
+    }
+    __syncthreads();
+    // (3) slots inside the reserved ranges
+    for (int base = e0; base < e1; base += kPrivThreads * kUnroll) {
+        int c[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) c[u] = icol[min(base + u * kPrivThreads + (int)threadIdx.x, e1 - 1)];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int p = base + u * kPrivThreads + (int)threadIdx.x;
+            if (p >= e1) continue;
+            const int row = r0 + last_le(sp, 0, rows - 1, p);
+            const unsigned off = (unsigned)(c[u] - lo);
+            const int slot = off < (unsigned)width ? atomicAdd(&bins[off], 1) : atomicAdd(&cursor[c[u]], 1);
+            keys[slot] = ((u64)(uint32_t)p << 32) | (uint32_t)row;
+        }
+    }
+}
+
+hipError_t launch_ccs_scatter(int n, int bw, const int* irp, const int* icol, int* cursor, u64* keys,
                               hipStream_t s) {
+    int rows = 0;
+    if (bw >= 0 && (int64_t)2 * bw + kPrivMinRows <= kScatBins) {
+        rows = std::min(kScatRows, (int)((kScatBins - 2 * (int64_t)bw) / kBlock * kBlock));
+        rows = std::min(rows, ((n + kBlock - 1) / kBlock) * kBlock);
+    }
+    if (rows >= kPrivMinRows || (rows > 0 && rows >= n)) {
+        const unsigned tiles = (unsigned)((n + rows - 1) / rows);
+        hipLaunchKernelGGL(k_ccs_scatter_priv, dim3(tiles), dim3(kPrivThreads), 0, s, n, bw, rows, irp, icol, cursor,
+                           keys);
+        return hipGetLastError();
+    }
     unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_col_walk<true>, dim3(blocks), dim3(kBlock), 0, s, n, irp, icol, cursor, keys);
     return hipGetLastError();

@@ -48,7 +48,7 @@ hipError_t launch_col_count(int n, int bw, const int* irp, const int* icol, int*
 hipError_t launch_col_scan(int n, const int* cnt, int* ccp, int* cursor, int* bsum,
                            int* mid_list, int* long_list, ColSummary* sum, hipStream_t s);
 size_t col_scan_bsum_count(int n);   // per array; the scan needs two (sums, maxima)
-hipError_t launch_ccs_scatter(int n, const int* irp, const int* icol, int* cursor,
+hipError_t launch_ccs_scatter(int n, int bw, const int* irp, const int* icol, int* cursor,
                               unsigned long long* keys, hipStream_t s);
 hipError_t launch_ccs_sort_small(int n, const int* ccp, unsigned long long* keys, const void* val,
                                  int vbytes, int* irow_t, void* val_t, hipStream_t s);
