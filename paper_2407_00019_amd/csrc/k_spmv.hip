@@ -91,8 +91,14 @@ k_spmv_crs_stream(int n, const int* __restrict__ irp, const int* __restrict__ ic
             prod[q] = (X)widen(ld_nt(&val[c0 + q])) * x[ld_nt(&icol[c0 + q])];
         __syncthreads();
         if (!lng) {
-            const int lo = max(a, c0), hi = min(b, c0 + cl);
-            for (int p = lo; p < hi; ++p) s += prod[p - c0];
+            // storage order; four LDS reads in flight ahead of the adds
+            const int lo = max(a, c0) - c0, hi = min(b, c0 + cl) - c0;
+            int p = lo;
+            for (; p + 4 <= hi; p += 4) {
+                const X q0 = prod[p], q1 = prod[p + 1], q2 = prod[p + 2], q3 = prod[p + 3];
+                s += q0; s += q1; s += q2; s += q3;
+            }
+            for (; p < hi; ++p) s += prod[p];
         }
         if (any_long) {
             // each long row in turn: the workgroup sums its part of the chunk
