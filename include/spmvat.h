@@ -300,7 +300,8 @@ typedef struct {
 /* Creates the server on the current device (allocates hbm_cap bytes and the
  * slots' streams).  SPMV_E_TOO_LARGE if the allocation fails. */
 spmv_status spmv_server_create(const spmv_server_config *cfg, spmv_server **out);
-/* Starts the scheduler thread; arrival times count from here. */
+/* Starts the dispatcher and the slots' worker threads; arrival times count
+ * from here. */
 spmv_status spmv_server_start(spmv_server *s);
 /* Queues a job (thread-safe); SPMV_E_ARG for an invalid descriptor.  A job
  * whose CRS footprint exceeds hbm_cap is reported with SPMV_E_TOO_LARGE. */

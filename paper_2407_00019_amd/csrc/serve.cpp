@@ -2,19 +2,19 @@
 // request, with the transformation amortised over the request's declared
 // number of SpMVs (the iteration-count discussion after the on-line phase).
 //
-// One scheduler thread owns the device side.  Jobs become visible at their
-// arrival time and wait in FIFO order; a job is admitted when a slot (one
-// HIP stream) is free and its CRS footprint fits in the device arena.  An
-// admitted job moves through:
-//   INGEST  host-to-device copies, row statistics, statistics read back
-//           through pinned memory -- all asynchronous, finished by an event;
-//   RUN     format choice from D_mat, the row lengths and k (the transformed
-//           format is allocated only if it fits now, else the job stays in
-//           CRS), the optional transformation, the chain of k SpMVs
-//           x_{t+1} = 2^-shift y_t, and the copy of y_k back to the host.
-// The loop never blocks on one job: it polls events, so work from different
-// jobs overlaps on the device and new jobs are admitted as slots and memory
-// free up.
+// A dispatcher thread makes jobs visible at their arrival time and admits
+// them in FIFO order: the head job waits until a slot is free and its CRS
+// block fits in the device arena.  Each slot (one HIP stream) has its own
+// worker thread, so the host work of one job (copies, launches, waits)
+// never holds up another's.  A worker carries its job through:
+//   INGEST  host-to-device copies, row statistics written straight into
+//           pinned memory, an event after them;
+//   RUN     format choice from D_mat, the bandwidth, the row lengths and k
+//           (the transformed format is allocated only if it fits now, else
+//           the job stays in CRS), the optional transformation, the chain of
+//           k SpMVs x_{t+1} = 2^-shift A x_t, and the copy of y_k back.
+// The device work of a job is the same whatever runs beside it, so its
+// result is too.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -103,23 +103,23 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-enum class SlotState { kFree, kIngest, kRun };
-
 struct Block {
     int64_t off = -1;
     size_t bytes = 0;
 };
 
+// One slot = one HIP stream and one worker thread that carries a job from
+// its copies to its result.
 struct Slot {
-    SlotState state = SlotState::kFree;
     hipStream_t stream = nullptr;
     hipEvent_t event = nullptr;
-    RowStats* host_stats = nullptr;   // pinned
+    RowStats* host_stats = nullptr;   // pinned, written by the statistics kernel
+    std::thread worker;
+    bool busy = false;                // a job is assigned (guarded by the server's mutex)
     spmv_job job{};
     spmv_job_result res{};
     spmv_plan plan;
     Block crs, fmt;
-    char* dev = nullptr;              // start of the CRS block
     int32_t *irp = nullptr, *icol = nullptr;
     float *val = nullptr, *x = nullptr, *y = nullptr;
     void* pwork = nullptr;
@@ -141,10 +141,12 @@ struct spmv_server {
     int device = 0;
     char* base = nullptr;
     spmv_arena arena{0};
+    std::mutex arena_mu;              // the arena is shared by the dispatcher and the workers
     std::vector<Slot> slots;
-    std::thread thread;
-    std::mutex mu;
-    std::condition_variable cv;
+    std::thread dispatcher;
+    std::mutex mu;                    // queues, results, slot assignment
+    std::condition_variable cv;       // completions (spmv_server_wait, the dispatcher)
+    std::condition_variable work_cv;  // assignments (the workers)
     std::deque<spmv_job> pending;     // submitted, sorted by arrival
     std::deque<spmv_job> ready;       // arrived, FIFO
     std::vector<spmv_job_result> done;
@@ -155,17 +157,37 @@ struct spmv_server {
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 
+    int64_t arena_alloc(size_t bytes) {
+        std::lock_guard<std::mutex> g(arena_mu);
+        return arena.alloc(bytes);
+    }
+    void arena_release(Block& b) {
+        if (b.off >= 0) {
+            std::lock_guard<std::mutex> g(arena_mu);
+            arena.release(b.off, b.bytes);
+        }
+        b = Block{};
+    }
+
+    void report(const spmv_job_result& r) {
+        std::lock_guard<std::mutex> g(mu);
+        done.push_back(r);
+        ++completed;
+        cv.notify_all();
+    }
+
+    // Ends the slot's job: frees its memory, records the result, frees the slot.
     void finish(Slot& s, int32_t status) {
-        if (s.fmt.off >= 0) arena.release(s.fmt.off, s.fmt.bytes);
-        if (s.crs.off >= 0) arena.release(s.crs.off, s.crs.bytes);
-        s.fmt = Block{};
-        s.crs = Block{};
+        arena_release(s.fmt);
+        arena_release(s.crs);
         s.res.status = status;
         s.res.done_s = now();
-        s.state = SlotState::kFree;
-        std::lock_guard<std::mutex> g(mu);
-        done.push_back(s.res);
-        ++completed;
+        {
+            std::lock_guard<std::mutex> g(mu);
+            done.push_back(s.res);
+            ++completed;
+            s.busy = false;
+        }
         cv.notify_all();
     }
 
@@ -176,26 +198,16 @@ struct spmv_server {
         r.arrival_s = j.arrival_s;
         r.admit_s = r.ready_s = r.done_s = now();
         r.format = -1;
-        std::lock_guard<std::mutex> g(mu);
-        done.push_back(r);
-        ++completed;
-        cv.notify_all();
+        report(r);
     }
 
-    // Copies in, enqueues the statistics.  False if the arena is full now.
-    bool admit(Slot& s, const spmv_job& j) {
-        const size_t need = crs_footprint(j);
-        const int64_t off = arena.alloc(need);
-        if (off < 0) return false;
-        s.job = j;
-        s.res = spmv_job_result{};
-        s.res.id = j.id;
-        s.res.arrival_s = j.arrival_s;
-        s.res.admit_s = now();
-        s.res.format = -1;
-        s.crs = Block{off, need};
-        s.res.device_bytes = need;
-        char* p = base + off;
+    bool wait_event(Slot& s) { return hipEventSynchronize(s.event) == hipSuccess; }
+
+    // INGEST: copies in (the CRS block was reserved at admission), row
+    // statistics written to pinned memory, an event after them.
+    spmv_status ingest(Slot& s) {
+        const spmv_job& j = s.job;
+        char* p = base + s.crs.off;
         s.irp = reinterpret_cast<int32_t*>(p); p += r256(4 * ((size_t)j.n + 1));
         s.icol = reinterpret_cast<int32_t*>(p); p += r256(4 * (size_t)j.nnz);
         s.val = reinterpret_cast<float*>(p); p += r256(4 * (size_t)j.nnz);
@@ -209,31 +221,32 @@ struct spmv_server {
         if (e == hipSuccess && j.nnz > 0)
             e = hipMemcpyAsync(s.val, j.val, 4 * (size_t)j.nnz, hipMemcpyHostToDevice, s.stream);
         if (e == hipSuccess) e = hipMemcpyAsync(s.x, j.x0, 4 * (size_t)j.n, hipMemcpyHostToDevice, s.stream);
+        if (e != hipSuccess) return SPMV_E_HIP;
         s.plan = spmv_plan();
-        spmv_status st = e == hipSuccess ? plan_begin(&s.plan, j.n, j.nnz, s.irp, s.icol, s.val, SPMV_F32, s.pwork,
-                                                      s.pwork_bytes, s.host_stats, s.stream)
-                                         : SPMV_E_HIP;
+        spmv_status st = plan_begin(&s.plan, j.n, j.nnz, s.irp, s.icol, s.val, SPMV_F32, s.pwork, s.pwork_bytes,
+                                    s.host_stats, s.stream);
         if (st == SPMV_OK && hipEventRecord(s.event, s.stream) != hipSuccess) st = SPMV_E_HIP;
-        if (st != SPMV_OK) {
-            (void)hipStreamSynchronize(s.stream);
-            finish(s, st);
-            return true;
-        }
-        s.state = SlotState::kIngest;
-        return true;
+        return st;
     }
 
-    // Statistics are back: choose the format, enqueue transformation + chain.
-    void launch_run(Slot& s) {
+    // RUN: format choice from D_mat, the row lengths and k (the transformed
+    // format is allocated only if it fits now, else the job stays in CRS),
+    // the optional transformation, the chain, the copy of y_k back.
+    spmv_status run(Slot& s) {
         spmv_status st = plan_finish(&s.plan, *s.host_stats);
-        if (st != SPMV_OK) { finish(s, st); return; }
+        if (st != SPMV_OK) return st;
         s.res.ready_s = now();
         s.res.d_mat = s.plan.st.d_mat;
         spmv_format f = SPMV_CRS;
         int v = 1;
         if (cfg.policy == 0) {
             at_decision why{};
-            const size_t limit = std::min(s.plan.limit, arena.largest());
+            size_t largest;
+            {
+                std::lock_guard<std::mutex> g(arena_mu);
+                largest = arena.largest();
+            }
+            const size_t limit = std::min(s.plan.limit, largest);
             if (at_choose_format_stats(&s.plan.st, SPMV_F32, limit, &cfg.table, s.job.k, &f, &v, &why) != SPMV_OK) {
                 f = SPMV_CRS;
                 v = 1;
@@ -246,7 +259,7 @@ struct spmv_server {
                 v = 1;
             } else {
                 const size_t need = r256(sz.bytes[0]) + r256(sz.bytes[1]);
-                const int64_t off = arena.alloc(need);
+                const int64_t off = arena_alloc(need);
                 if (off < 0) {
                     f = SPMV_CRS;   // not enough memory now: stay in CRS
                     v = 1;
@@ -260,7 +273,7 @@ struct spmv_server {
                     b.bytes[1] = sz.bytes[1];
                     st = f == SPMV_ELL_ROW ? csr_to_ell(&s.plan, 0, &b, nullptr, 0, s.stream)
                                            : csr_to_coo(&s.plan, 0, &b, nullptr, 0, s.stream);
-                    if (st != SPMV_OK) { (void)hipStreamSynchronize(s.stream); finish(s, st); return; }
+                    if (st != SPMV_OK) return st;
                 }
             }
         }
@@ -286,58 +299,78 @@ struct spmv_server {
                     st = SPMV_E_HIP;
                 in = s.y;
             }
-            if (st != SPMV_OK) { (void)hipStreamSynchronize(s.stream); finish(s, st); return; }
+            if (st != SPMV_OK) return st;
         }
         // `in` holds y_k after the last step in either scheme
         hipError_t e = hipMemcpyAsync(s.job.y_out, in, 4 * (size_t)s.job.n, hipMemcpyDeviceToHost, s.stream);
         if (e == hipSuccess) e = hipEventRecord(s.event, s.stream);
-        if (e != hipSuccess) { (void)hipStreamSynchronize(s.stream); finish(s, SPMV_E_HIP); return; }
-        s.state = SlotState::kRun;
+        return e == hipSuccess ? SPMV_OK : SPMV_E_HIP;
     }
 
-    void loop() {
+    void work(Slot& s) {
         (void)hipSetDevice(device);
-        while (!stop.load(std::memory_order_relaxed)) {
-            bool busy = false;
-            const double t = now();
+        for (;;) {
             {
-                std::lock_guard<std::mutex> g(mu);
-                while (!pending.empty() && pending.front().arrival_s <= t) {
-                    ready.push_back(pending.front());
-                    pending.pop_front();
-                }
+                std::unique_lock<std::mutex> lk(mu);
+                work_cv.wait(lk, [&] { return s.busy || stop.load(); });
+                if (!s.busy) return;   // stopping, nothing assigned
             }
-            for (Slot& s : slots) {
-                if (s.state == SlotState::kFree) continue;
-                busy = true;
-                const hipError_t q = hipEventQuery(s.event);
-                if (q == hipErrorNotReady) continue;
-                if (q != hipSuccess) { finish(s, SPMV_E_HIP); continue; }
-                if (s.state == SlotState::kIngest) launch_run(s);
-                else finish(s, SPMV_OK);
+            spmv_status st = ingest(s);
+            if (st == SPMV_OK && !wait_event(s)) st = SPMV_E_HIP;
+            if (st == SPMV_OK) st = run(s);
+            if (st == SPMV_OK && !wait_event(s)) st = SPMV_E_HIP;
+            if (st != SPMV_OK) (void)hipStreamSynchronize(s.stream);
+            finish(s, st);
+        }
+    }
+
+    // Arrivals and admission in arrival order: the head job waits until a
+    // slot is free and its CRS block fits in the arena.
+    void dispatch() {
+        (void)hipSetDevice(device);
+        std::unique_lock<std::mutex> lk(mu);
+        while (!stop.load()) {
+            const double t = now();
+            while (!pending.empty() && pending.front().arrival_s <= t) {
+                ready.push_back(pending.front());
+                pending.pop_front();
             }
-            // admission, in arrival order: a job waits until a slot and its memory are free
-            for (;;) {
-                spmv_job j;
-                {
-                    std::lock_guard<std::mutex> g(mu);
-                    if (ready.empty()) break;
-                    j = ready.front();
-                }
+            bool admitted = false;
+            while (!ready.empty()) {
+                const spmv_job j = ready.front();
                 if (crs_footprint(j) > arena.cap) {
-                    { std::lock_guard<std::mutex> g(mu); ready.pop_front(); }
+                    ready.pop_front();
+                    lk.unlock();
                     fail_unadmitted(j, SPMV_E_TOO_LARGE);
+                    lk.lock();
                     continue;
                 }
                 Slot* free_slot = nullptr;
-                for (Slot& s : slots)
-                    if (s.state == SlotState::kFree) { free_slot = &s; break; }
-                if (!free_slot || !admit(*free_slot, j)) break;
-                { std::lock_guard<std::mutex> g(mu); ready.pop_front(); }
-                busy = true;
+                for (Slot& sl : slots)
+                    if (!sl.busy) { free_slot = &sl; break; }
+                if (!free_slot) break;
+                const size_t need = crs_footprint(j);
+                const int64_t off = arena_alloc(need);
+                if (off < 0) break;
+                ready.pop_front();
+                Slot& sl = *free_slot;
+                sl.job = j;
+                sl.res = spmv_job_result{};
+                sl.res.id = j.id;
+                sl.res.arrival_s = j.arrival_s;
+                sl.res.admit_s = t;
+                sl.res.format = -1;
+                sl.res.device_bytes = need;
+                sl.crs = Block{off, need};
+                sl.fmt = Block{};
+                sl.busy = true;
+                admitted = true;
             }
-            if (busy) std::this_thread::yield();
-            else std::this_thread::sleep_for(std::chrono::microseconds(20));
+            if (admitted) work_cv.notify_all();
+            // wake at the next arrival, at a completion, or after a short wait
+            double wait_s = 2e-4;
+            if (!pending.empty()) wait_s = std::min(wait_s, std::max(0.0, pending.front().arrival_s - now()));
+            cv.wait_for(lk, std::chrono::duration<double>(wait_s));
         }
     }
 };
@@ -371,7 +404,8 @@ SPMV_API spmv_status spmv_server_start(spmv_server* s) {
     if (!s || s->started) return SPMV_E_ARG;
     s->t0 = Clock::now();
     s->started = true;
-    s->thread = std::thread([s] { s->loop(); });
+    for (Slot& sl : s->slots) sl.worker = std::thread([s, &sl] { s->work(sl); });
+    s->dispatcher = std::thread([s] { s->dispatch(); });
     return SPMV_OK;
 }
 
@@ -387,6 +421,7 @@ SPMV_API spmv_status spmv_server_submit(spmv_server* s, const spmv_job* job) {
     while (it != s->pending.begin() && std::prev(it)->arrival_s > j.arrival_s) --it;
     s->pending.insert(it, j);
     ++s->submitted;
+    s->cv.notify_all();   // the dispatcher re-reads the queue
     return SPMV_OK;
 }
 
@@ -408,8 +443,16 @@ SPMV_API int32_t spmv_server_results(spmv_server* s, spmv_job_result* out, int32
 
 SPMV_API void spmv_server_destroy(spmv_server* s) {
     if (!s) return;
-    s->stop.store(true);
-    if (s->thread.joinable()) s->thread.join();
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop.store(true);
+    }
+    s->cv.notify_all();
+    s->work_cv.notify_all();
+    if (s->dispatcher.joinable()) s->dispatcher.join();
+    // a worker finishes the job it holds, then sees the stop flag
+    for (Slot& sl : s->slots)
+        if (sl.worker.joinable()) sl.worker.join();
     for (Slot& sl : s->slots) {
         if (sl.stream) { (void)hipStreamSynchronize(sl.stream); (void)hipStreamDestroy(sl.stream); }
         if (sl.event) (void)hipEventDestroy(sl.event);
