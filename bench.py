@@ -397,6 +397,18 @@ def serving(count):
     return res
 
 
+def cpu_model():
+    """The host CPU's model name (Linux), for the baseline's record."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def kernel_source_sha():
     import hashlib
     h = hashlib.sha256()
@@ -428,7 +440,7 @@ def cpu_baseline(m, x, budget_s):
     return {"value": round(b / t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"{len(times)} CRS SpMVs of {m.name} (median {t * 1e3:.1f} ms each) and one pass of "
                       f"COO-Row / ELL-Row / CCS transformations",
-            "host_cpus": os.cpu_count(),
+            "host_cpus": os.cpu_count(), "cpu_model": cpu_model(),
             "tt_coo_row": round(t_coo / t, 3), "tt_ell_row": round(t_ell / t, 3), "tt_ccs": round(t_ccs / t, 3)}
 
 
