@@ -137,32 +137,44 @@ def summarize(res) -> dict:
             "span_s": round(last - first, 4), "formats": fmts}
 
 
-def compare(jobs_host, slots, hbm_cap, rate, log=print) -> dict:
-    """Both policies on one trace: burst first (all jobs at t = 0) to find
-    the always-CRS capacity, then Poisson arrivals at `rate` jobs/s (rate
-    'auto': 70% of that capacity)."""
+def _median_run(runs, key):
+    """The run whose `key` is the median of the runs (runs: list of summaries)."""
+    order = sorted(runs, key=lambda r: r[key])
+    return order[len(order) // 2]
+
+
+def compare(jobs_host, slots, hbm_cap, rate, log=print, repeats: int = 3) -> dict:
+    """Both policies on one trace, each replayed `repeats` times, alternating
+    policies so that drifts of the machine hit both alike: burst first (all
+    jobs at t = 0) to find the always-CRS capacity, then Poisson arrivals at
+    `rate` jobs/s (rate 'auto': 70% of that capacity).  Each policy reports
+    its median run (by jobs/s for the burst, by p50 for Poisson) and every
+    run's figure."""
     table = load_table()
-    out = {"slots": slots, "hbm_cap_bytes": hbm_cap}
+    out = {"slots": slots, "hbm_cap_bytes": hbm_cap, "repeats": repeats}
     zeros = [0.0] * len(jobs_host)
-    burst = {}
-    for name, pol in (("crs", 1), ("auto", 0)):
-        res, wall = run(jobs_host, pol, slots, hbm_cap, table, zeros)
-        burst[name] = summarize(res)
-        log(f"[serve] burst {name}: {burst[name]}")
-    out["burst"] = burst
-    if rate == "auto":
-        lam = 0.7 * burst["crs"]["jobs_per_s"]
-    else:
-        lam = float(rate)
+    runs = {"crs": [], "auto": []}
+    for rep in range(repeats):
+        for name, pol in (("crs", 1), ("auto", 0)):
+            res, wall = run(jobs_host, pol, slots, hbm_cap, table, zeros)
+            runs[name].append(summarize(res))
+            log(f"[serve] burst {name} #{rep}: {runs[name][-1]}")
+    out["burst"] = {name: dict(_median_run(r, "jobs_per_s"), runs_jobs_per_s=[x["jobs_per_s"] for x in r])
+                    for name, r in runs.items()}
+    lam = 0.7 * out["burst"]["crs"]["jobs_per_s"] if rate == "auto" else float(rate)
     u = np.random.default_rng(20240700019).random(len(jobs_host))
     arr = np.cumsum(-np.log1p(-u) / lam)
     arr -= arr[0]
-    poisson = {}
-    for name, pol in (("crs", 1), ("auto", 0)):
-        res, wall = run(jobs_host, pol, slots, hbm_cap, table, arr.tolist())
-        poisson[name] = summarize(res)
-        log(f"[serve] poisson {name}: {poisson[name]}")
-    out["poisson"] = {"rate_per_s": round(lam, 2), **poisson}
+    runs = {"crs": [], "auto": []}
+    for rep in range(repeats):
+        for name, pol in (("crs", 1), ("auto", 0)):
+            res, wall = run(jobs_host, pol, slots, hbm_cap, table, arr.tolist())
+            runs[name].append(summarize(res))
+            log(f"[serve] poisson {name} #{rep}: {runs[name][-1]}")
+    out["poisson"] = {"rate_per_s": round(lam, 2)}
+    for name, r in runs.items():
+        out["poisson"][name] = dict(_median_run(r, "p50_ms"), runs_p50_ms=[x["p50_ms"] for x in r],
+                                    runs_p99_ms=[x["p99_ms"] for x in r])
     return out
 
 
@@ -174,6 +186,7 @@ def main(argv=None):
     ap.add_argument("--cap-gb", type=float, default=200.0)
     ap.add_argument("--rate", default="auto")
     ap.add_argument("--n-max", type=float, default=5e5)
+    ap.add_argument("--repeats", type=int, default=3)
     a = ap.parse_args(argv)
     t0 = time.time()
     specs = gen.serving_jobs(a.jobs, rate_per_s=0.0, n_max=a.n_max)
@@ -181,7 +194,7 @@ def main(argv=None):
     print(f"[serve] built {len(jobs)} jobs ({sum(j.nnz for j in jobs) / 1e6:.1f}M nonzeros) in "
           f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     out = compare(jobs, a.slots, int(a.cap_gb * (1 << 30)), a.rate,
-                  log=lambda s: print(s, file=sys.stderr, flush=True))
+                  log=lambda s: print(s, file=sys.stderr, flush=True), repeats=a.repeats)
     print(json.dumps(out), flush=True)
 
 
