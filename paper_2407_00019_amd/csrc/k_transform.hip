@@ -84,11 +84,13 @@ hipError_t launch_expand_ptr(int n, const int* ptr, int* out, hipStream_t s) {
 }
 
 // ------------------------------------------------ Phase I: column counts
-// and the scatter.  Both walk a tile of 256 rows with one row per lane:
-// the tile's column indices (contiguous in CRS) are staged in LDS with
-// coalesced loads, then every lane steps through its own row.  For banded
-// and stencil matrices the lanes of a wave then touch consecutive columns at
-// each step, so a wave's atomics coalesce into a few cache lines.
+// and the scatter.  Matrices of small bandwidth use the LDS-privatised
+// kernels below (a tile's columns all fall in a window that fits in LDS).
+// Otherwise both walk a tile of 256 rows with one row per lane: the tile's
+// column indices (contiguous in CRS) are staged in LDS with coalesced loads,
+// then every lane steps through its own row.  For banded and stencil
+// matrices the lanes of a wave then touch consecutive columns at each step,
+// so a wave's atomics coalesce into a few cache lines.
 
 constexpr int kRowTileCap = 8192;   // column indices staged per pass
 

@@ -326,3 +326,46 @@ def test_convert_values_bits_match_oracle():
         got = stored_bits(spmvat.convert_values(vd, dt))
         want = oracle.round_values(dt, v)
         assert np.array_equal(got, want), dt
+
+
+def band_edges(n, bw, seed):
+    """Rows i with columns i-1, i, i+1 and i - bw, i + bw where they exist,
+    plus a dense row: bandwidth exactly bw, sorted rows."""
+    rng = np.random.default_rng(seed)
+    i = np.arange(n)
+    cols = [i - bw, i - 1, i, i + 1, i + bw]
+    mask = [(c >= 0) & (c < n) for c in cols]
+    lens = np.sum(mask, axis=0)
+    dense = n // 2
+    extra = np.arange(max(0, dense - bw), min(n, dense + bw + 1), 97)
+    rows = []
+    for r in range(n):
+        c = [int(cc[r]) for cc, mm in zip(cols, mask) if mm[r]]
+        if r == dense:
+            c = sorted(set(c) | set(extra.tolist()))
+        rows.append(c)
+    lens = np.array([len(r) for r in rows])
+    irp = np.zeros(n + 1, np.int64)
+    irp[1:] = np.cumsum(lens)
+    icol = np.concatenate([np.array(r, np.int32) for r in rows])
+    return gen.Crs(n, irp.astype(np.int32), icol, rng.standard_normal(icol.shape[0]), f"band_edges_{bw}")
+
+
+@pytest.mark.parametrize("bw", [17888, 17900, 17921])
+def test_ccs_around_the_privatised_window_limits(bw):
+    """Column counts are privatised in LDS up to bandwidth 17920, the scatter
+    up to 17888: matrices on both sides of each limit give the oracle's CCS
+    bit for bit, and the bandwidth statistic is exact."""
+    spmvat = lib_ready()
+    m = band_edges(60000, bw, 40 + bw)
+    assert oracle.bandwidth(m.n, m.irp, m.icol) == bw
+    irp, icol, val = to_dev(m)
+    plan = spmvat.Plan(irp, icol, val)
+    assert plan.stats.bandwidth == bw
+    ccp, irow_t, val_t = plan.to_ccs()
+    o_ccp, o_irow_t, o_val_t = oracle.csr_to_ccs(m.n, m.irp, m.icol, m.val)
+    assert np.array_equal(host(ccp), o_ccp)
+    assert np.array_equal(host(irow_t), o_irow_t)
+    assert np.array_equal(bits(host(val_t)), bits(o_val_t))
+    assert plan.stats.max_col == int(np.diff(o_ccp).max())
+    plan.close()
