@@ -147,9 +147,19 @@ class PathRunner:
         # one plan to size the buffers
         plan = spmvat.spmv_plan_create(self.n, self.nnz, irp, icol, val, self.dtype, self.work)
         self.stats = spmvat.spmv_plan_stats(plan)
+        # ELL-Row only where the plan's default memory guard admits it (the
+        # power-law matrix's would take about 166 GB): then it is reported
+        # as refused, as the library refuses it
+        st, sz = spmvat.spmv_buffer_sizes(plan, spmvat.ELL_ROW)
+        self.ell_row = st == spmvat.SPMV_OK
+        self.ell_row_bytes = int(sz.bytes[0] + sz.bytes[1]) if self.ell_row else None
         spmvat.spmv_plan_set_limit(plan, 1 << 45)
+        if not self.ell_row:
+            s2, sz2 = spmvat.spmv_buffer_sizes(plan, spmvat.ELL_ROW)
+            self.ell_row_bytes = int(sz2.bytes[0] + sz2.bytes[1]) if s2 == spmvat.SPMV_OK else None
         self.buf = {}
-        for f in (spmvat.COO_ROW, spmvat.CCS, spmvat.ELL_ROW) if with_column else (spmvat.COO_ROW, spmvat.ELL_ROW):
+        fmts = [spmvat.COO_ROW] + ([spmvat.CCS] if with_column else []) + ([spmvat.ELL_ROW] if self.ell_row else [])
+        for f in fmts:
             self.buf[f] = alloc_like(spmvat, plan, f, self.vt, self.dev)
         if with_column:
             spmvat.csr_to_ccs(plan, self.buf[spmvat.CCS][0], self.buf[spmvat.CCS][1])
@@ -167,17 +177,20 @@ class PathRunner:
                  self.work)
         sp.spmv_plan_set_limit(plan, 1 << 45)
         if table is not None:
-            self.decision = sp.at_choose_format(plan, table, 0)
+            self.decision = sp.at_choose_format(plan, table, 0)        # the paper's rule
+            self.decision_k100 = sp.at_choose_format(plan, table, 100)  # amortised over 100 SpMVs
         T(f"{L}coo_row", sp.csr_to_coo, plan, 0, self.buf[sp.COO_ROW][0])
         if self.with_column and not spmv_only:
             T(f"{L}ccs", sp.csr_to_ccs, plan, self.buf[sp.CCS][0], self.buf[sp.CCS][1])
             T(f"{L}coo_col", sp.csr_to_coo, plan, 1, self.buf[sp.COO_COL][0])
             T(f"{L}ell_col", sp.csr_to_ell, plan, 1, self.buf[sp.ELL_COL][0])
-        T(f"{L}ell_row", sp.csr_to_ell, plan, 0, self.buf[sp.ELL_ROW][0])
+        if self.ell_row:
+            T(f"{L}ell_row", sp.csr_to_ell, plan, 0, self.buf[sp.ELL_ROW][0])
         R = self.reps
         for v in self.variants:
             T(f"{L}spmv_crs{v}", sp.spmv_exec, plan, sp.CRS, v, self.x, self.y, reps=R)
-        T(f"{L}spmv_ell_row", sp.spmv_exec, plan, sp.ELL_ROW, 0, self.x, self.y, reps=R)
+        if self.ell_row:
+            T(f"{L}spmv_ell_row", sp.spmv_exec, plan, sp.ELL_ROW, 0, self.x, self.y, reps=R)
         T(f"{L}spmv_coo_row", sp.spmv_exec, plan, sp.COO_ROW, 0, self.x, self.y, reps=R)
         if self.with_column and not spmv_only:
             T(f"{L}spmv_coo_col", sp.spmv_exec, plan, sp.COO_COL, 0, self.x, self.y, reps=R)
@@ -204,7 +217,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="stencil27_128", choices=["stencil27_128", "laplace64"])
+    ap.add_argument("--workload", default="stencil27_128", choices=["stencil27_128", "laplace64", "powerlaw"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-precision", action="store_true", help="skip the reduced-precision rows")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-oracle SpMV sample")
@@ -229,8 +242,11 @@ def main():
 
     dev = torch.device("cuda:0")
     t0 = time.time()
-    m = gen.stencil27_128() if args.workload == "stencil27_128" else gen.laplace_64x64()
-    cfg_seed = gen.seed_for(2 if args.workload == "stencil27_128" else 1)
+    builders = {"laplace64": (gen.laplace_64x64, 1), "stencil27_128": (gen.stencil27_128, 2),
+                "powerlaw": (gen.powerlaw, 3)}
+    build_m, cfg_index = builders[args.workload]
+    m = build_m()
+    cfg_seed = gen.seed_for(cfg_index)
     x64 = gen.x_uniform(m.n, cfg_seed)
     log(f"[bench] workload {m.name}: n={m.n} nnz={m.nnz} generated in {time.time() - t0:.1f}s")
     irp = torch.from_numpy(m.irp).to(dev)
@@ -301,6 +317,8 @@ def main():
                   "coo_col": ("coo_col", "spmv_coo_col", wc), "ell_col": ("ell_col", "spmv_ell_col", wc)}
     # rates and ratios from the per-step medians (a host stall between two
     # events inflates one step's mean); "us" keeps the mean
+    if not r0.ell_row:
+        del spmv_names["ell_row"]
     for name, (fmt, key, width) in spmv_names.items():
         b = spmv_bytes(fmt, n, nnz, width, 8, 8)
         g = gbs(b, med[key])
@@ -311,15 +329,20 @@ def main():
     t_crs1 = min(med["spmv_crs8"], med[f"spmv_crs{v_sub}"])      # the strong CRS kernel
     transforms = {}
     for kind, width in (("stats", 0), ("coo_row", 0), ("ccs", 0), ("coo_col", 0), ("ell_row", w), ("ell_col", wc)):
+        if kind == "ell_row" and not r0.ell_row:
+            transforms[kind] = {"refused": "memory guard", "ell_bytes": r0.ell_row_bytes}
+            continue
         b = transform_bytes(kind, n, nnz, width, 8)
         transforms[kind] = {"us": round(ms[kind] * 1e3, 2), "median_us": round(med[kind] * 1e3, 2),
                             "gbs": round(gbs(b, med[kind]), 1),
                             "tt_vs_crs_scalar": round(med[kind] / t_crs0, 3),
                             "tt_vs_crs_best": round(med[kind] / t_crs1, 3), "bytes": int(b)}
-    sp_ell = {"vs_crs_scalar": round(t_crs0 / med["spmv_ell_row"], 3),
-              "vs_crs_best": round(t_crs1 / med["spmv_ell_row"], 3)}
-    r_ell = {"vs_crs_scalar": round(sp_ell["vs_crs_scalar"] / (med["ell_row"] / t_crs0), 4),
-             "vs_crs_best": round(sp_ell["vs_crs_best"] / (med["ell_row"] / t_crs1), 4)}
+    sp_ell = r_ell = None
+    if r0.ell_row:
+        sp_ell = {"vs_crs_scalar": round(t_crs0 / med["spmv_ell_row"], 3),
+                  "vs_crs_best": round(t_crs1 / med["spmv_ell_row"], 3)}
+        r_ell = {"vs_crs_scalar": round(sp_ell["vs_crs_scalar"] / (med["ell_row"] / t_crs0), 4),
+                 "vs_crs_best": round(sp_ell["vs_crs_best"] / (med["ell_row"] / t_crs1), 4)}
 
     precision = {}
     if not args.no_precision:
@@ -328,7 +351,9 @@ def main():
         y64 = r0.outputs(spmvat.CRS, 8)
         for r, tag, vb in ((runners[1], "f32", 4), (runners[2], "bf16", 2)):
             entry = {}
-            for fmt, key, code, var in (("crs", "spmv_crs8", spmvat.CRS, 8), ("ell_row", "spmv_ell_row", spmvat.ELL_ROW, 0)):
+            pairs = [("crs", "spmv_crs8", spmvat.CRS, 8)] + ([("ell_row", "spmv_ell_row", spmvat.ELL_ROW, 0)]
+                                                             if r.ell_row else [])
+            for fmt, key, code, var in pairs:
                 b_ = spmv_bytes(fmt, n, nnz, w, vb, 4)
                 t_ms = med[f"{tag}:{key}"]          # median: robust to host stalls between events
                 y = r.outputs(code, var)
@@ -371,14 +396,15 @@ def main():
         "sp_ell_row": sp_ell, "r_ell_row": r_ell,
         "at_decision": {"table": os.path.relpath(table_path, ROOT) if table_path else None,
                         "d_star": table.d_star if math.isfinite(table.d_star) else "inf",
-                        "choice": spmvat.FORMAT_NAMES[r0.decision[0]] if hasattr(r0, "decision") else None},
+                        "choice": spmvat.FORMAT_NAMES[r0.decision[0]] if hasattr(r0, "decision") else None,
+                        "choice_k100": spmvat.FORMAT_NAMES[r0.decision_k100[0]] if hasattr(r0, "decision_k100") else None},
         "precision": precision,
         "kernel_source_sha": kernel_source_sha(),
     }
     if args.serve_jobs > 0:
         out["serving"] = serving(args.serve_jobs)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(m, x64, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(m, x64, args.cpu_seconds, with_ell=r0.ell_row)
     print(json.dumps(out), flush=True)
 
 
@@ -419,7 +445,7 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(m, x, budget_s):
+def cpu_baseline(m, x, budget_s, with_ell=True):
     """The CPU oracle as it stands (single-threaded C, binary64) on the same
     matrix: CRS SpMV repeated for about budget_s seconds; its GB/s uses the
     same algorithmic bytes as the GPU figure."""
@@ -435,13 +461,16 @@ def cpu_baseline(m, x, budget_s):
     b = spmv_bytes("crs", n, nnz, 0, 8, 8)
     # one pass of the oracle's transformations for its own TT figures
     t0 = time.perf_counter(); oracle.csr_to_coo_row(n, m.irp); t_coo = time.perf_counter() - t0
-    t0 = time.perf_counter(); oracle.csr_to_ell_row(n, m.irp, m.icol, m.val); t_ell = time.perf_counter() - t0
+    t_ell = None
+    if with_ell:
+        t0 = time.perf_counter(); oracle.csr_to_ell_row(n, m.irp, m.icol, m.val); t_ell = time.perf_counter() - t0
     t0 = time.perf_counter(); oracle.csr_to_ccs(n, m.irp, m.icol, m.val); t_ccs = time.perf_counter() - t0
     return {"value": round(b / t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"{len(times)} CRS SpMVs of {m.name} (median {t * 1e3:.1f} ms each) and one pass of "
-                      f"COO-Row / ELL-Row / CCS transformations",
+                      f"COO-Row / {'ELL-Row / ' if with_ell else ''}CCS transformations",
             "host_cpus": os.cpu_count(), "cpu_model": cpu_model(),
-            "tt_coo_row": round(t_coo / t, 3), "tt_ell_row": round(t_ell / t, 3), "tt_ccs": round(t_ccs / t, 3)}
+            "tt_coo_row": round(t_coo / t, 3), "tt_ell_row": round(t_ell / t, 3) if t_ell is not None else None,
+            "tt_ccs": round(t_ccs / t, 3)}
 
 
 if __name__ == "__main__":
