@@ -54,13 +54,33 @@ size_t crs_bytes(const spmv_plan* p) {
     return (size_t)(p->n + 1) * 4 + (size_t)p->nnz * (4 + (size_t)vbytes_of(p->dt));
 }
 
-// CCS workspace layout.
+// CRS -> CCS algorithm by the matrix's structure: scattered columns (the
+// bandwidth too wide for the LDS-privatised window) with n <= 2^22 take the
+// two-level counting sort; everything else column counts, a scatter and
+// per-column sorts (privatised in LDS when the window fits).
+bool ccs_bucketed(int32_t n, int32_t bw) { return n <= (1 << kCcsRowBits) && !ccs_privatised(bw); }
+
+// CCS workspace layout: bucketed -- count table, its chunk sums, summary,
+// level-1 keys and values; else -- counts/cursors, scan sums and maxima,
+// long-column lists, summary, keys, merge scratch.
 struct CcsWs {
-    size_t cursor, bsum, mid, lng, sum, keys, tmp, total;
+    size_t cursor, bsum, mid, lng, sum, keys, tmp;   // per-column sort path
+    size_t table, csum, bkey, bval;                  // bucketed path
+    size_t total;
 };
-CcsWs ccs_ws(int32_t n, int64_t nnz) {
+CcsWs ccs_ws(int32_t n, int64_t nnz, int vb, int32_t bw) {
     CcsWs w{};
     size_t o = 0;
+    if (ccs_bucketed(n, bw)) {
+        const CcsGeom g = ccs_geom(n);
+        w.table = o; o += round_up((size_t)g.table * 4, kAlign);
+        w.csum = o;  o += round_up((size_t)g.chunks * 4, kAlign);
+        w.sum = o;   o += round_up(sizeof(ColSummary), kAlign);
+        w.bkey = o;  o += round_up((size_t)nnz * 4, kAlign);
+        w.bval = o;  o += round_up((size_t)nnz * vb, kAlign);
+        w.total = o;
+        return w;
+    }
     w.cursor = o; o += round_up((size_t)n * 4, kAlign);
     w.bsum = o;   o += round_up(col_scan_bsum_count(n) * 8, kAlign);
     const size_t nmid = std::min<size_t>((size_t)n, (size_t)(nnz / (kSortSmall + 1)) + 1);
@@ -211,7 +231,7 @@ SPMV_API spmv_status spmv_buffer_sizes(const spmv_plan* p, spmv_format f, spmv_s
             out->bytes[0] = (n + 1) * 4;
             out->bytes[1] = nnz * 4;
             out->bytes[2] = nnz * vb;
-            out->workspace = ccs_ws(p->n, p->nnz).total;
+            out->workspace = ccs_ws(p->n, p->nnz, vbytes_of(p->dt), p->st.bandwidth).total;
             return SPMV_OK;
         case SPMV_COO_COL:
             out->bytes[0] = nnz * 4;
@@ -264,13 +284,36 @@ SPMV_API spmv_status csr_to_ccs(spmv_plan* p, const spmv_buffers* out, void* wor
     if (!work || !aligned16(work) || work_bytes < need.workspace) return SPMV_E_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int vb = vbytes_of(p->dt);
-    const CcsWs w = ccs_ws(p->n, p->nnz);
+    const CcsWs w = ccs_ws(p->n, p->nnz, vb, p->st.bandwidth);
     char* base = static_cast<char*>(work);
     int32_t* ccp = static_cast<int32_t*>(out->ptr[0]);
     int32_t* irow_t = static_cast<int32_t*>(out->ptr[1]);
     void* val_t = out->ptr[2];
     ColSummary* dsum = reinterpret_cast<ColSummary*>(base + w.sum);
     ColSummary cs{};
+
+    if (ccs_bucketed(p->n, p->st.bandwidth)) {
+        // level 1 (count table, its scan, ordered distribution to column
+        // blocks) and level 2 (ordered placement inside each block); one sync
+        // at the end for the longest column
+        const CcsGeom g = ccs_geom(p->n);
+        HIP_TRY(p, launch_ccs_bucketed(g, p->n, p->nnz, p->irp, p->icol, p->val, vb,
+                                       reinterpret_cast<int32_t*>(base + w.table),
+                                       reinterpret_cast<int32_t*>(base + w.csum),
+                                       reinterpret_cast<uint32_t*>(base + w.bkey), base + w.bval, ccp, irow_t, val_t,
+                                       dsum, s));
+        HIP_TRY(p, hipMemcpyAsync(&cs, dsum, sizeof(cs), hipMemcpyDeviceToHost, s));
+        HIP_TRY(p, hipStreamSynchronize(s));
+        if ((int64_t)cs.total != p->nnz) {
+            p->err = "column-block counts do not add up to nnz";
+            return SPMV_E_HIP;
+        }
+        p->ccp = ccp; p->irow_t = irow_t; p->val_t = val_t; p->has_ccs = true;
+        p->st.max_col = cs.max_len;
+        p->jcol = nullptr; p->has_coo_col = false;   // a rebuilt CCS invalidates the formats built on it
+        p->ellc_w = -1; p->ellc_val = nullptr; p->ellc_row = nullptr;
+        return SPMV_OK;
+    }
     int32_t* cursor = reinterpret_cast<int32_t*>(base + w.cursor);
     int32_t* bsum = reinterpret_cast<int32_t*>(base + w.bsum);
     int32_t* mid = reinterpret_cast<int32_t*>(base + w.mid);

@@ -362,6 +362,8 @@ k_ccs_scatter_priv(int n, int bw, int rows_per_tile, const int* __restrict__ irp
     }
 }
 
+bool ccs_privatised(int bw) { return bw >= 0 && (int64_t)2 * bw + kPrivMinRows <= kScatBins; }
+
 hipError_t launch_ccs_scatter(int n, int bw, const int* irp, const int* icol, int* cursor, u64* keys,
                               hipStream_t s) {
     int rows = 0;

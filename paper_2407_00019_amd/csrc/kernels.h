@@ -59,6 +59,25 @@ hipError_t launch_ccs_sort_mid(int count, const int* list, const int* ccp, unsig
 // across sorted chunks instead (no scratch, slower).
 hipError_t launch_ccs_sort_long(int start, int len, unsigned long long* keys, unsigned long long* tmp,
                                 const void* val, int vbytes, int* irow_t, void* val_t, hipStream_t s);
+// The LDS-privatised counts and scatter apply (the window of a tile's
+// columns fits in LDS) for matrix bandwidth bw.
+bool ccs_privatised(int bw);
+// Two-level stable counting sort (column blocks of 2^kCcsBlockBits columns,
+// keys packing the column within the block above a kCcsRowBits-bit row):
+// the CCS path for scattered columns with n <= 2^kCcsRowBits.
+constexpr int kCcsBlockBits = 10;
+constexpr int kCcsRowBits = 22;
+struct CcsGeom {
+    int nb, nb_bits;     // column blocks, bits of a block index
+    int rows, tiles;     // rows per level-1 tile, tiles
+    int waves;           // waves per level-1 workgroup
+    int64_t table;       // tiles x blocks counts
+    int64_t chunks;      // 4096-count chunks of the table scan
+};
+CcsGeom ccs_geom(int n);
+hipError_t launch_ccs_bucketed(const CcsGeom& g, int n, int64_t nnz, const int* irp, const int* icol,
+                               const void* val, int vbytes, int* table, int* csum, uint32_t* bkey, void* bval,
+                               int* ccp, int* irow_t, void* val_t, ColSummary* sum, hipStream_t s);
 hipError_t launch_ell_pack(int n, int width, const int* ptr, const int* idx, const void* val,
                            int vbytes, void* ell_val, int* ell_idx, hipStream_t s);
 
