@@ -132,6 +132,8 @@ k_spmv_crs_stream(int n, const int* __restrict__ irp, const int* __restrict__ ic
 
 // ------------------------------------------------------------- ELL
 
+constexpr int kEllUnrolled = 32;   // binary64 ELL-Row widths with a fully unrolled kernel
+
 template <typename V, typename X>
 __global__ void __launch_bounds__(kBlock)
 k_spmv_ell_row(int n, int width, const V* __restrict__ ev, const int* __restrict__ ec, const X* __restrict__ x,
@@ -147,8 +149,11 @@ k_spmv_ell_row(int n, int width, const V* __restrict__ ev, const int* __restrict
 }
 
 // Two consecutive rows per thread: one 2-element load per slot for values
-// and indices (n even keeps every k*n + i pair aligned).
-template <typename V, typename X>
+// and indices (n even keeps every k*n + i pair aligned).  W > 0 is the
+// width known at compile time: the slot loop is unrolled whole, so every
+// load of a thread is in flight before the first product; W = 0 takes the
+// width at run time.
+template <typename V, typename X, int W>
 __global__ void __launch_bounds__(kBlock)
 k_spmv_ell_row2(int n, int width, const V* __restrict__ ev, const int* __restrict__ ec, const X* __restrict__ x,
                 X* __restrict__ y, X alpha) {
@@ -156,14 +161,20 @@ k_spmv_ell_row2(int n, int width, const V* __restrict__ ev, const int* __restric
     if (i >= n) return;
     X s0 = 0, s1 = 0;
     size_t off = (size_t)i;
-#pragma unroll 8
-    for (int k = 0; k < width; ++k, off += (size_t)n) {
+    auto slot = [&](size_t o) {
         V v0, v1;
         int c0, c1;
-        load2_nt(&ev[off], v0, v1);
-        load2_nt(&ec[off], c0, c1);
+        load2_nt(&ev[o], v0, v1);
+        load2_nt(&ec[o], c0, c1);
         s0 += (X)widen(v0) * x[c0];
         s1 += (X)widen(v1) * x[c1];
+    };
+    if constexpr (W > 0) {
+#pragma unroll
+        for (int k = 0; k < W; ++k, off += (size_t)n) slot(off);
+    } else {
+#pragma unroll 8
+        for (int k = 0; k < width; ++k, off += (size_t)n) slot(off);
     }
     y[i] = s0 * alpha;
     y[i + 1] = s1 * alpha;
@@ -467,9 +478,23 @@ hipError_t launch_spmv_ell_row(int dtype, int n, int width, const void* ev, cons
                                void* y, double alpha, hipStream_t s) {
     if (dtype == 0 && n % 2 == 0) {
         // binary64: two rows per thread measured faster; narrower values lose
-        // parallelism without gaining wider loads, so they keep one row
-        hipLaunchKernelGGL((k_spmv_ell_row2<double, double>), dim3(grid_for(n / 2, kBlock)), dim3(kBlock), 0, s, n,
-                           width, (const double*)ev, ec, (const double*)x, (double*)y, alpha);
+        // parallelism without gaining wider loads, so they keep one row.
+        // Widths up to kEllUnrolled get their own fully unrolled kernel.
+        const dim3 grid(grid_for(n / 2, kBlock));
+#define ELL2(W) hipLaunchKernelGGL((k_spmv_ell_row2<double, double, W>), grid, dim3(kBlock), 0, s, n, width, \
+                                   (const double*)ev, ec, (const double*)x, (double*)y, alpha)
+#define ELL2_CASE(W) case W: ELL2(W); break;
+        switch (width) {
+            ELL2_CASE(1) ELL2_CASE(2) ELL2_CASE(3) ELL2_CASE(4) ELL2_CASE(5) ELL2_CASE(6) ELL2_CASE(7) ELL2_CASE(8)
+            ELL2_CASE(9) ELL2_CASE(10) ELL2_CASE(11) ELL2_CASE(12) ELL2_CASE(13) ELL2_CASE(14) ELL2_CASE(15)
+            ELL2_CASE(16) ELL2_CASE(17) ELL2_CASE(18) ELL2_CASE(19) ELL2_CASE(20) ELL2_CASE(21) ELL2_CASE(22)
+            ELL2_CASE(23) ELL2_CASE(24) ELL2_CASE(25) ELL2_CASE(26) ELL2_CASE(27) ELL2_CASE(28) ELL2_CASE(29)
+            ELL2_CASE(30) ELL2_CASE(31) ELL2_CASE(32)
+            default: ELL2(0); break;
+        }
+#undef ELL2_CASE
+#undef ELL2
+        static_assert(kEllUnrolled == 32, "the switch above lists widths 1 .. kEllUnrolled");
     } else {
         SPMV_DISPATCH(dtype, hipLaunchKernelGGL((k_spmv_ell_row<V, X>), dim3(grid_for(n, kBlock)), dim3(kBlock), 0,
                                                 s, n, width, (const V*)ev, ec, (const X*)x, (X*)y, (X)alpha));
