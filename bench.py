@@ -41,6 +41,20 @@ def log(*a):
 # What the method itself must move: each array read or written once, x and
 # y once each, ELL padding included (the method computes it).
 
+def stream_lanes(n, nnz):
+    """Lanes per row the library's stream CRS kernel picks (its template
+    argument, so the kernel's name in a profile): one per 32 entries of the
+    mean row, doubled while the grid holds fewer than 1024 workgroups and a
+    lane keeps at least four entries."""
+    mean = nnz / n if n > 0 else 0.0
+    g = 1
+    while g < 64 and 32.0 * 2 * g <= mean:
+        g *= 2
+    while g < 64 and n * g // 256 < 1024 and 4.0 * 2 * g <= mean:
+        g *= 2
+    return g
+
+
 def spmv_bytes(fmt, n, nnz, width, vb, xb):
     if fmt == "crs":
         return (vb + 4) * nnz + 4 * (n + 1) + 2 * xb * n
@@ -372,7 +386,7 @@ def main():
     ell2 = f"k_spmv_ell_row2<double, double, {w if 0 < w <= 32 else 0}>"   # widths 1..32 are unrolled kernels
     kernel_names = {"ell_row": ell2 if n % 2 == 0 else "k_spmv_ell_row<double, double>",
                     f"crs_subwave{wsub}": f"k_spmv_crs_vector<double, double, {wsub}>",
-                    "crs_stream": "k_spmv_crs_stream<double, double>",
+                    "crs_stream": f"k_spmv_crs_stream<double, double, {stream_lanes(n, nnz)}>",
                     "crs_scalar": "k_spmv_crs_scalar<double, double>", "coo_row": "k_spmv_coo_row<double, double>",
                     "coo_col": "k_spmv_coo_col<double, double>", "ell_col": "k_spmv_ell_col<double, double>"}
     traffic = None

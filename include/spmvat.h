@@ -104,6 +104,11 @@ typedef struct {
  * per second; 0 marks a missing entry. */
 #define AT_DBUCKETS 8
 #define AT_LOCAL_BAND 65536
+/* The k-aware rule transforms only when the estimated cost with the
+ * transformation, times AT_K_MARGIN, stays below the cost of staying in
+ * CRS: the model's per-job estimates err by about ten percent (measured over
+ * the serving stream), so a smaller predicted gain is not acted on. */
+#define AT_K_MARGIN 1.1
 typedef struct {
     double c;                                 /* R_ell threshold (the paper uses 1.0) */
     double d_star;                            /* ELL-Row when D_mat < d_star; +inf: always */
@@ -120,7 +125,8 @@ typedef struct {
     double t_crs_hat;      /* estimated CRS SpMV seconds (best CRS variant) */
     double t_fmt_hat;      /* estimated SpMV seconds in the chosen format */
     double t_trans_hat;    /* estimated transformation seconds into it */
-    double k_break_even;   /* TT / (1 - 1/SP) for the chosen format; 0 for CRS */
+    double k_break_even;   /* TT / (1 - 1/SP) for the chosen format (where its cost
+                            * equals CRS's, before AT_K_MARGIN); 0 for CRS */
 } at_decision;
 
 /* ------------------------------------------------------------- planning */
@@ -222,8 +228,9 @@ spmv_status at_table_build(const double *d, const double *r, const int32_t *feas
 /* Host only.  On-line phase of section 2.2.  k_repeats <= 0: the paper's
  * rule, ELL_ROW when D_mat < D* and ELL-Row fits the plan's limit, else
  * CRS (variant 1, the library's CRS kernel, which D* is measured against).  k_repeats > 0 and a calibrated table: the option with
- * the least estimated transformation + k_repeats SpMVs among CRS (both
- * variants), COO_ROW and ELL_ROW (when it fits); ties keep CRS. */
+ * the least estimated transformation + k_repeats SpMVs among COO_ROW and
+ * ELL_ROW (when it fits), if AT_K_MARGIN times that cost is below
+ * k_repeats SpMVs of the faster CRS variant; otherwise CRS. */
 spmv_status at_choose_format(const spmv_plan *p, const at_table *t, int64_t k_repeats,
                              spmv_format *fmt, int *variant, at_decision *why);
 

@@ -270,18 +270,19 @@ def choose_paper(d_mat: float, dstar: float) -> str:
     return "ell_row" if d_mat < dstar else "crs"
 
 
-def choose_k_aware(k: int, t_crs: float, candidates: dict) -> str:
+def choose_k_aware(k: int, t_crs: float, candidates: dict, margin: float = 1.0) -> str:
     """Amortised decision over k SpMVs (the iteration-count discussion of
-    section 2.2): the option f minimising t_trans_f + k t_f, where
-    `candidates` maps a name to (t_trans, t_spmv) and the no-transform
-    option 'crs' costs k * t_crs.  Ties go to 'crs'."""
-    best, cost = "crs", k * t_crs
+    section 2.2): `candidates` maps a name to (t_trans, t_spmv); the one
+    minimising t_trans + k t_spmv (the first in name order on a tie) is
+    taken if margin times its cost is below k * t_crs, the cost of staying
+    in CRS; otherwise 'crs'."""
+    best, cost = None, float("inf")
     for name in sorted(candidates):
         tt, ts = candidates[name]
         c = tt + k * ts
         if c < cost:
             best, cost = name, c
-    return best
+    return best if best is not None and margin * cost < k * t_crs else "crs"
 
 
 def rel_l2(y, yref) -> float:

@@ -32,6 +32,7 @@ DTYPE_OF_TORCH = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16, 
 TORCH_OF_DTYPE = {v: k for k, v in DTYPE_OF_TORCH.items()}
 AT_DBUCKETS = 8
 AT_LOCAL_BAND = 65536
+AT_K_MARGIN = 1.1        # the k-aware rule's required predicted gain (spmvat.h)
 AT_DBUCKET_EDGES = (0.0625, 0.125, 0.25, 0.5, 1.0, 2.0, 4.0)
 
 

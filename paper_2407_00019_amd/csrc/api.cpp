@@ -396,7 +396,7 @@ spmv_status spmvat::plan_exec(const spmv_plan* p, spmv_format f, int variant, co
             if (variant < 0 || variant > 8) return SPMV_E_ARG;
             const bool stream = variant == 8 || variant == 1;
             if (variant == 0) HIP_TRY(p, launch_spmv_crs_scalar(dt, p->n, p->irp, p->icol, p->val, x, y, alpha, s));
-            else if (stream) HIP_TRY(p, launch_spmv_crs_stream(dt, p->n, p->irp, p->icol, p->val, x, y, alpha, s));
+            else if (stream) HIP_TRY(p, launch_spmv_crs_stream(dt, p->n, p->nnz, p->irp, p->icol, p->val, x, y, alpha, s));
             else {
                 const int w = 1 << (variant - 1);
                 HIP_TRY(p, launch_spmv_crs_vector(dt, w, p->n, p->irp, p->icol, p->val, x, y, alpha, s));
@@ -516,7 +516,8 @@ SPMV_API spmv_status at_choose_format_stats(const spmv_stats* st, spmv_dtype dt,
         if (d.feasible_ell && st->d_mat < t->d_star) { *fmt = SPMV_ELL_ROW; *variant = 0; }
         else { *fmt = SPMV_CRS; *variant = 1; }
     } else {
-        // least estimated transformation + k SpMVs; ties keep CRS
+        // least estimated transformation + k SpMVs among the transformed
+        // formats; it replaces CRS only by more than the model's error
         d.rule = 1;
         const int b = dbucket(st->d_mat);
         const int loc = st->bandwidth <= AT_LOCAL_BAND ? 0 : 1;
@@ -529,15 +530,18 @@ SPMV_API spmv_status at_choose_format_stats(const spmv_stats* st, spmv_dtype dt,
         spmv_format bf = SPMV_CRS;
         int bv = tc1 < tc0 ? 1 : 0;
         const double tcrs = std::min(tc0, tc1);
-        double best = k * tcrs, bt = tcrs, btr = 0;
+        double best = std::numeric_limits<double>::infinity(), bt = tcrs, btr = 0;
+        spmv_format cf = SPMV_CRS;
         const spmv_format cands[2] = {SPMV_COO_ROW, SPMV_ELL_ROW};
         for (spmv_format f : cands) {
             if (f == SPMV_ELL_ROW && !d.feasible_ell) continue;
             const double ts = est(spmv_bytes(*st, dt, f), t->spmv_bps[loc][f][0][b], f == SPMV_COO_ROW ? 2 : 1);
             const double tr = est(trans_bytes(*st, dt, f), t->trans_bps[loc][f][b], 1);
             const double cost = tr + k * ts;
-            if (cost < best) { best = cost; bf = f; bv = 0; bt = ts; btr = tr; }
+            if (cost < best) { best = cost; cf = f; bt = ts; btr = tr; }
         }
+        if (cf != SPMV_CRS && AT_K_MARGIN * best < k * tcrs) { bf = cf; bv = 0; }
+        else { bt = tcrs; btr = 0; }
         *fmt = bf; *variant = bv;
         d.t_crs_hat = tcrs; d.t_fmt_hat = bt; d.t_trans_hat = btr;
         if (bf != SPMV_CRS && bt < tcrs) d.k_break_even = (btr / tcrs) / (1.0 - bt / tcrs);

@@ -5,11 +5,12 @@
 //  CRS scalar     one thread per row (the plain CRS loop).
 //  CRS vector     a power-of-two lane group per row, coalesced row loads,
 //                 butterfly reduction inside the group.
-//  CRS stream     a workgroup takes 256 rows; their entries, contiguous in
-//                 CRS, are read coalesced in chunks and their products kept
-//                 in LDS; each row is then summed by its own thread in
-//                 storage order, except rows of more than 256 entries, which
-//                 the whole workgroup reduces.
+//  CRS stream     a workgroup takes 256/G rows; their entries, contiguous
+//                 in CRS, are read coalesced in chunks and their products
+//                 kept in LDS; each row is then summed by G lanes (G = 1: by
+//                 its own thread in storage order), except rows of more than
+//                 256 entries, which the whole workgroup reduces.  G grows
+//                 with the mean row length and on small matrices.
 //  ELL-Row        Fig. 3: thread per row, slot loop inside, slot-major loads
 //                 coalesced across the wave; no reduction step.
 //  ELL-Column     thread per column, y(row) += val * x(col) with atomics.
@@ -61,23 +62,30 @@ k_spmv_crs_vector(int n, const int* __restrict__ irp, const int* __restrict__ ic
 constexpr int kStreamCap = 2048;   // products staged in LDS per chunk
 constexpr int kStreamLong = 256;   // rows longer than this are summed by the whole workgroup
 
-template <typename V, typename X>
+// G lanes per row, 256/G rows per workgroup.  The lanes of a row take its
+// staged products in a stride of G (storage order when G = 1, four LDS reads
+// in flight ahead of the adds) and meet in a butterfly at the end.
+template <typename V, typename X, int G>
 __global__ void __launch_bounds__(kBlock)
 k_spmv_crs_stream(int n, const int* __restrict__ irp, const int* __restrict__ icol, const V* __restrict__ val,
                   const X* __restrict__ x, X* __restrict__ y, X alpha) {
+    constexpr int kRows = kBlock / G;
     __shared__ X prod[kStreamCap];
-    __shared__ int sp[kBlock + 1];
+    __shared__ int sp[kRows + 1];
     __shared__ unsigned long long s_long[kBlock / kWave];
     __shared__ X s_red[kBlock / kWave];
-    const int r0 = (int)xcd_block(blockIdx.x, gridDim.x) * kBlock;
-    const int rows = min(kBlock, n - r0);
+    const int r0 = (int)xcd_block(blockIdx.x, gridDim.x) * kRows;
+    const int rows = min(kRows, n - r0);
     const int t = threadIdx.x;
     for (int c = t; c <= rows; c += kBlock) sp[c] = irp[r0 + c];
     __syncthreads();
     const int end = sp[rows];
-    const int a = t < rows ? sp[t] : end, b = t < rows ? sp[t + 1] : end;
+    const int row = t / G, lane = t % G;
+    const int a = row < rows ? sp[row] : end, b = row < rows ? sp[row + 1] : end;
     const bool lng = (b - a) > kStreamLong;
-    const unsigned long long m = __ballot(lng);
+    // long rows as a bit mask indexed by row (thread t tests row t)
+    const bool lt = t < rows && (sp[t + 1] - sp[t]) > kStreamLong;
+    const unsigned long long m = __ballot(lt);
     if ((t & (kWave - 1)) == 0) s_long[t / kWave] = m;
     __syncthreads();
     bool any_long = false;
@@ -91,14 +99,13 @@ k_spmv_crs_stream(int n, const int* __restrict__ irp, const int* __restrict__ ic
             prod[q] = (X)widen(ld_nt(&val[c0 + q])) * x[ld_nt(&icol[c0 + q])];
         __syncthreads();
         if (!lng) {
-            // storage order; four LDS reads in flight ahead of the adds
             const int lo = max(a, c0) - c0, hi = min(b, c0 + cl) - c0;
-            int p = lo;
-            for (; p + 4 <= hi; p += 4) {
-                const X q0 = prod[p], q1 = prod[p + 1], q2 = prod[p + 2], q3 = prod[p + 3];
+            int p = lo + lane;
+            for (; p + 3 * G < hi; p += 4 * G) {
+                const X q0 = prod[p], q1 = prod[p + G], q2 = prod[p + 2 * G], q3 = prod[p + 3 * G];
                 s += q0; s += q1; s += q2; s += q3;
             }
-            for (; p < hi; ++p) s += prod[p];
+            for (; p < hi; p += G) s += prod[p];
         }
         if (any_long) {
             // each long row in turn: the workgroup sums its part of the chunk
@@ -115,7 +122,7 @@ k_spmv_crs_stream(int n, const int* __restrict__ irp, const int* __restrict__ ic
                     for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off, kWave);
                     if ((t & (kWave - 1)) == 0) s_red[t / kWave] = part;
                     __syncthreads();
-                    if (t == r) {
+                    if (t == r * G) {
                         X tot = 0;
 #pragma unroll
                         for (int k2 = 0; k2 < kBlock / kWave; ++k2) tot += s_red[k2];
@@ -127,7 +134,9 @@ k_spmv_crs_stream(int n, const int* __restrict__ irp, const int* __restrict__ ic
         }
         __syncthreads();
     }
-    if (t < rows) y[r0 + t] = s * alpha;
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
+    if (lane == 0 && row < rows) y[r0 + row] = s * alpha;
 }
 
 // ------------------------------------------------------------- ELL
@@ -438,10 +447,35 @@ static inline unsigned grid_for(int64_t items, int per_block) {
         default: { typedef f16_t V; typedef float X; CALL; break; }  \
     }
 
-hipError_t launch_spmv_crs_stream(int dtype, int n, const int* irp, const int* icol, const void* val,
+// Lanes per row for the stream kernel: about one per 32 entries of the mean
+// row, doubled while the grid would hold fewer than 1024 workgroups and each
+// lane still gets at least four entries (measured on banded and lognormal
+// rows of 1e3 .. 2e6 rows and 3 .. 129 entries per row).
+int crs_stream_lanes(int n, int64_t nnz) {
+    const double mean = n > 0 ? (double)nnz / n : 0.0;
+    int g = 1;
+    while (g < 64 && 32.0 * (2 * g) <= mean) g *= 2;
+    while (g < 64 && (int64_t)n * g / kBlock < 1024 && 4.0 * (2 * g) <= mean) g *= 2;
+    return g;
+}
+
+hipError_t launch_spmv_crs_stream(int dtype, int n, int64_t nnz, const int* irp, const int* icol, const void* val,
                                   const void* x, void* y, double alpha, hipStream_t s) {
-    SPMV_DISPATCH(dtype, hipLaunchKernelGGL((k_spmv_crs_stream<V, X>), dim3(grid_for(n, kBlock)), dim3(kBlock),
-                                            0, s, n, irp, icol, (const V*)val, (const X*)x, (X*)y, (X)alpha));
+    const int g = crs_stream_lanes(n, nnz);
+#define CRSS(G) hipLaunchKernelGGL((k_spmv_crs_stream<V, X, G>), dim3(grid_for(n, kBlock / G)), dim3(kBlock), 0, s, \
+                                   n, irp, icol, (const V*)val, (const X*)x, (X*)y, (X)alpha)
+    SPMV_DISPATCH(dtype, {
+        switch (g) {
+            case 1: CRSS(1); break;
+            case 2: CRSS(2); break;
+            case 4: CRSS(4); break;
+            case 8: CRSS(8); break;
+            case 16: CRSS(16); break;
+            case 32: CRSS(32); break;
+            default: CRSS(64); break;
+        }
+    });
+#undef CRSS
     return hipGetLastError();
 }
 

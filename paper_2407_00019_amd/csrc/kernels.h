@@ -89,7 +89,8 @@ hipError_t launch_fill_zero(void* y, int64_t bytes, hipStream_t s);
 hipError_t launch_scale_pow2(int dtype, int n, int shift, const void* in, void* out, hipStream_t s);
 hipError_t launch_spmv_crs_scalar(int dtype, int n, const int* irp, const int* icol, const void* val,
                                   const void* x, void* y, double alpha, hipStream_t s);
-hipError_t launch_spmv_crs_stream(int dtype, int n, const int* irp, const int* icol, const void* val,
+int crs_stream_lanes(int n, int64_t nnz);   // lanes per row the stream kernel uses
+hipError_t launch_spmv_crs_stream(int dtype, int n, int64_t nnz, const int* irp, const int* icol, const void* val,
                                   const void* x, void* y, double alpha, hipStream_t s);
 hipError_t launch_spmv_crs_vector(int dtype, int width, int n, const int* irp, const int* icol,
                                   const void* val, const void* x, void* y, double alpha, hipStream_t s);

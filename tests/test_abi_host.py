@@ -129,7 +129,7 @@ def test_k_aware_choice_matches_oracle(k, dtype):
         "coo_row": ((4 * (n + 1) + 4 * nnz) / 3.0e12 + 2e-6, coo_b / 2.5e12 + 4e-6),
         "ell_row": (((vb + 4) * nnz + 4 * (n + 1) + ell_b - 2 * xb * n) / 2.0e12 + 2e-6, ell_b / 4.0e12 + 2e-6),
     }
-    want = oracle.choose_k_aware(k, tcrs, cands)
+    want = oracle.choose_k_aware(k, tcrs, cands, spmvat.AT_K_MARGIN)
     f, v, why = spmvat.at_choose_format_stats(st, dtype, 1 << 40, t, k)
     got = {spmvat.CRS: "crs", spmvat.COO_ROW: "coo_row", spmvat.ELL_ROW: "ell_row"}[f]
     assert got == want
@@ -139,6 +139,28 @@ def test_k_aware_choice_matches_oracle(k, dtype):
     else:
         ts = cands[got][1]
         assert why.k_break_even == pytest.approx((cands[got][0] / tcrs) / (1 - ts / tcrs))
+
+
+def test_k_aware_needs_a_gain_beyond_the_margin():
+    """A transformation predicted to save less than the margin keeps CRS;
+    one predicted to save more converts.  The constant is the header's."""
+    spmvat = _lib()
+    with open(os.path.join(ROOT, "include", "spmvat.h")) as fh:
+        hdr = fh.read()
+    assert f"#define AT_K_MARGIN {spmvat.AT_K_MARGIN}" in hdr
+    n, nnz, w = 100000, 2_600_000, 26
+    st = _stats(n, nnz, w, 0.0)
+    crs_b = 12 * nnz + 4 * (n + 1) + 16 * n
+    ell_b = 12 * n * w + 16 * n
+    for gain, want in ((1.05, spmvat.CRS), (1.2, spmvat.ELL_ROW)):
+        # ELL-Row `gain` times faster per byte-normalised SpMV, transformation free
+        ell_rate = 1e12 * gain * ell_b / crs_b
+        t = _calibrated(spmvat, 1e12, 1e12, 1e9, ell_rate, 1e9, 1e30)
+        f, v, why = spmvat.at_choose_format_stats(st, 0, 1 << 40, t, 1000)
+        assert f == want, (gain, f)
+        cands = {"ell_row": (0.0, crs_b / 1e12 / gain)}
+        want_o = "crs" if want == spmvat.CRS else "ell_row"
+        assert oracle.choose_k_aware(1000, crs_b / 1e12, cands, spmvat.AT_K_MARGIN) == want_o
 
 
 def test_cost_model_cell_follows_locality_and_d_bucket():

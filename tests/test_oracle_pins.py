@@ -366,6 +366,12 @@ def test_k_aware_break_even():
     assert oracle.choose_k_aware(1, t_crs, both) == "crs"
     assert oracle.choose_k_aware(3, t_crs, both) == "coo_row"
     assert oracle.choose_k_aware(100, t_crs, both) == "ell_row"
+    # with a margin m the break-even moves to k > m TT / (1 - m/SP):
+    # m = 1.1 gives k > 3.3 / 0.45 = 7.33
+    assert oracle.choose_k_aware(7, t_crs, {"ell_row": (t_tr, t_f)}, 1.1) == "crs"
+    assert oracle.choose_k_aware(8, t_crs, {"ell_row": (t_tr, t_f)}, 1.1) == "ell_row"
+    # a format less than m times faster never pays, whatever k
+    assert oracle.choose_k_aware(10**9, t_crs, {"ell_row": (0.0, 0.95)}, 1.1) == "crs"
 
 
 # ------------------------------------------------------ value rounding (RNE)
