@@ -369,3 +369,50 @@ def test_ccs_around_the_privatised_window_limits(bw):
     assert np.array_equal(bits(host(val_t)), bits(o_val_t))
     assert plan.stats.max_col == int(np.diff(o_ccp).max())
     plan.close()
+
+
+def _stream_lanes(n, nnz):
+    # the stream kernel's lanes per row, restated from its launch rule: one
+    # per 32 entries of the mean row, doubled while the grid holds fewer than
+    # 1024 workgroups of 256/G rows and a lane keeps at least four entries
+    mean = nnz / n
+    g = 1
+    while g < 64 and 64 * g <= mean:
+        g *= 2
+    while g < 64 and n * g // 256 < 1024 and 8 * g <= mean:
+        g *= 2
+    return g
+
+
+@pytest.mark.parametrize("lanes,mean", [(1, 5), (2, 10), (4, 20), (8, 40), (16, 80), (32, 160), (64, 300)])
+def test_stream_crs_every_lane_count(lanes, mean):
+    """The stream CRS kernel at each lanes-per-row count it can pick, on rows
+    around the mean plus empty rows and rows longer than 256 entries (summed
+    by the whole workgroup) at workgroup edges: binary64 within 1e-13 of the
+    oracle, bitwise on small-integer data."""
+    import torch
+    spmvat = lib_ready()
+    n = 3000
+    rng = np.random.default_rng(lanes)
+    lengths = np.clip(rng.poisson(mean, n), 0, n).astype(np.int32)
+    rows = 256 // lanes
+    for r in (0, 1, rows - 1, rows, n // 2, n - 1):
+        lengths[r] = 700 if r % 2 == 0 else 300
+    lengths[[5, rows + 1, n - 2]] = 0
+    m = gen.random_rows(n, lengths, 40 + lanes)
+    assert _stream_lanes(n, int(m.irp[-1])) == lanes
+    for integer in (False, True):
+        val = np.round(m.val * 4) if integer else m.val
+        mm = gen.Crs(n, m.irp, m.icol, val, m.name)
+        x64 = np.round(gen.x_uniform(n, 9) * 8) if integer else gen.x_uniform(n, 9)
+        irp, icol, vd = to_dev(mm)
+        xd = torch.from_numpy(x64).to("cuda:0")
+        plan = spmvat.Plan(irp, icol, vd)
+        yref = oracle.spmv_crs(n, mm.irp, mm.icol, mm.val, x64)
+        for variant in (1, 8):
+            y = host(plan.spmv(spmvat.CRS, xd, variant=variant))
+            if integer:
+                assert np.array_equal(y, yref), (lanes, variant)
+            else:
+                assert oracle.rel_l2(y, yref) <= TOL64, (lanes, variant)
+        plan.close()
