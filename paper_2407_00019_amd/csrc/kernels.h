@@ -13,7 +13,7 @@ struct RowStats {
     int32_t max_len;
     uint32_t min_len;            // starts at 0xffffffff
     uint32_t flags;              // 1 irp[0]!=0, 2 irp[n]!=nnz, 4 decreasing irp, 8 column out of range
-    int32_t max_band;            // max |i - j| over each row's first and last entries
+    int32_t max_band;            // max |i - j| over every stored entry
 };
 
 // Column-count summary written by the CCS scan (read back by the host).
