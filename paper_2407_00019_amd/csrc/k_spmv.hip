@@ -12,7 +12,9 @@
 //                 256 entries, which the whole workgroup reduces.  G grows
 //                 with the mean row length and on small matrices.
 //  ELL-Row        Fig. 3: thread per row, slot loop inside, slot-major loads
-//                 coalesced across the wave; no reduction step.
+//                 coalesced across the wave; no reduction step.  Matrices
+//                 with few rows and wide rows take Fig. 4's outer-parallel
+//                 form instead: a row's slots split over P threads.
 //  ELL-Column     thread per column, y(row) += val * x(col) with atomics.
 //  COO-Row        Fig. 2's entry-chunk partition as a segmented reduction:
 //                 8 consecutive entries per thread, a segmented scan across
@@ -142,6 +144,7 @@ k_spmv_crs_stream(int n, const int* __restrict__ irp, const int* __restrict__ ic
 // ------------------------------------------------------------- ELL
 
 constexpr int kEllUnrolled = 32;   // binary64 ELL-Row widths with a fully unrolled kernel
+constexpr int kEllMaxParts = 16;   // most threads sharing one ELL-Row row
 
 template <typename V, typename X>
 __global__ void __launch_bounds__(kBlock)
@@ -187,6 +190,36 @@ k_spmv_ell_row2(int n, int width, const V* __restrict__ ev, const int* __restric
     }
     y[i] = s0 * alpha;
     y[i + 1] = s1 * alpha;
+}
+
+// Fig. 4's outer-parallel ELL-Row for matrices with few rows: the slots of
+// a row are split over P threads (part p takes slots p, p + P, ...), each
+// part sums its slots in order, and the P partial sums meet in LDS and are
+// added in part order (the paper's private partial y and serial reduction,
+// at the granularity of one row).  A workgroup holds 256/P rows, part-major,
+// so each wave's loads cover consecutive rows of one slot plane when
+// 256/P >= 64.
+template <typename V, typename X, int P>
+__global__ void __launch_bounds__(kBlock)
+k_spmv_ell_row_split(int n, int width, const V* __restrict__ ev, const int* __restrict__ ec,
+                     const X* __restrict__ x, X* __restrict__ y, X alpha) {
+    constexpr int kRows = kBlock / P;
+    __shared__ X part[kBlock];
+    const int r = (int)threadIdx.x % kRows, p = (int)threadIdx.x / kRows;
+    const int i = (int)xcd_block(blockIdx.x, gridDim.x) * kRows + r;
+    X s = 0;
+    if (i < n) {
+        size_t off = (size_t)p * n + i;
+#pragma unroll 4
+        for (int k = p; k < width; k += P, off += (size_t)P * n) s += (X)widen(ld_nt(&ev[off])) * x[ld_nt(&ec[off])];
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (p == 0 && i < n) {
+#pragma unroll
+        for (int q = 1; q < P; ++q) s += part[q * kRows + r];
+        y[i] = s * alpha;
+    }
 }
 
 template <typename V, typename X>
@@ -508,9 +541,31 @@ hipError_t launch_spmv_crs_vector(int dtype, int width, int n, const int* irp, c
     return hipGetLastError();
 }
 
+// Threads per row of ELL-Row: 1, doubled while the grid would hold fewer
+// than 1024 workgroups and each thread keeps at least four slots.
+int ell_row_parts(int n, int width) {
+    int p = 1;
+    while (p < kEllMaxParts && (int64_t)n * p / kBlock < 1024 && 4 * (2 * p) <= width) p *= 2;
+    return p;
+}
+
 hipError_t launch_spmv_ell_row(int dtype, int n, int width, const void* ev, const int* ec, const void* x,
                                void* y, double alpha, hipStream_t s) {
-    if (dtype == 0 && n % 2 == 0) {
+    const int parts = ell_row_parts(n, width);
+    if (parts > 1) {
+#define ELLS(P) hipLaunchKernelGGL((k_spmv_ell_row_split<V, X, P>), dim3(grid_for(n, kBlock / P)), dim3(kBlock), 0, \
+                                   s, n, width, (const V*)ev, ec, (const X*)x, (X*)y, (X)alpha)
+        SPMV_DISPATCH(dtype, {
+            switch (parts) {
+                case 2: ELLS(2); break;
+                case 4: ELLS(4); break;
+                case 8: ELLS(8); break;
+                default: ELLS(16); break;
+            }
+        });
+#undef ELLS
+        static_assert(kEllMaxParts == 16, "the switch above lists 2 .. kEllMaxParts");
+    } else if (dtype == 0 && n % 2 == 0) {
         // binary64: two rows per thread measured faster; narrower values lose
         // parallelism without gaining wider loads, so they keep one row.
         // Widths up to kEllUnrolled get their own fully unrolled kernel.

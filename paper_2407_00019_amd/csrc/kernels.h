@@ -94,6 +94,7 @@ hipError_t launch_spmv_crs_stream(int dtype, int n, int64_t nnz, const int* irp,
                                   const void* x, void* y, double alpha, hipStream_t s);
 hipError_t launch_spmv_crs_vector(int dtype, int width, int n, const int* irp, const int* icol,
                                   const void* val, const void* x, void* y, double alpha, hipStream_t s);
+int ell_row_parts(int n, int width);   // threads per row ELL-Row uses (1: Fig. 3, more: Fig. 4)
 hipError_t launch_spmv_ell_row(int dtype, int n, int width, const void* ev, const int* ec,
                                const void* x, void* y, double alpha, hipStream_t s);
 hipError_t launch_spmv_ell_col(int dtype, int n, int width, const void* ev, const int* er,

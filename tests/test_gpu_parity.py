@@ -416,3 +416,48 @@ def test_stream_crs_every_lane_count(lanes, mean):
             else:
                 assert oracle.rel_l2(y, yref) <= TOL64, (lanes, variant)
         plan.close()
+
+
+def _ell_parts(n, width):
+    # threads per row of ELL-Row, restated from its launch rule: doubled
+    # while the grid holds fewer than 1024 workgroups and each thread keeps
+    # at least four slots, at most 16
+    p = 1
+    while p < 16 and n * p // 256 < 1024 and 8 * p <= width:
+        p *= 2
+    return p
+
+
+@pytest.mark.parametrize("parts,width", [(1, 5), (2, 12), (4, 20), (8, 40), (16, 100)])
+def test_ell_row_outer_parallel_every_split(parts, width):
+    """ELL-Row with a row's slots split over 1..16 threads (Fig. 4's
+    outer-parallel form) on rows of every length up to the width, empty rows
+    included: binary64 within 1e-13 of the oracle's Fig. 3 loop, bitwise on
+    small-integer data; the ELL arrays themselves stay bit-exact."""
+    import torch
+    spmvat = lib_ready()
+    n = 3000
+    rng = np.random.default_rng(100 + parts)
+    lengths = rng.integers(0, width + 1, n).astype(np.int32)
+    lengths[[0, n // 2, n - 1]] = width
+    lengths[[1, 7]] = 0
+    m = gen.random_rows(n, lengths, 60 + parts)
+    assert _ell_parts(n, int(lengths.max())) == parts
+    for integer in (False, True):
+        val = np.round(m.val * 4) if integer else m.val
+        mm = gen.Crs(n, m.irp, m.icol, val, m.name)
+        x64 = np.round(gen.x_uniform(n, 11) * 8) if integer else gen.x_uniform(n, 11)
+        irp, icol, vd = to_dev(mm)
+        xd = torch.from_numpy(x64).to("cuda:0")
+        plan = spmvat.Plan(irp, icol, vd)
+        (ev, ec), w = plan.to_ell()
+        want_v, want_c = oracle.csr_to_ell_row(n, mm.irp, mm.icol, mm.val)[:2]
+        assert w == width
+        assert np.array_equal(bits(host(ev)), bits(want_v)) and np.array_equal(host(ec), want_c)
+        y = host(plan.spmv(spmvat.ELL_ROW, xd))
+        yref = oracle.spmv_ell_row(n, w, want_v, want_c, x64)
+        if integer:
+            assert np.array_equal(y, yref), parts
+        else:
+            assert oracle.rel_l2(y, yref) <= TOL64, parts
+        plan.close()
