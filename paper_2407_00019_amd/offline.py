@@ -15,7 +15,14 @@ amortised (k-aware) decision: algorithmic bytes per second of each format,
 variant and transformation per locality class (bandwidth <= 65536 or not)
 and D_mat bucket.
 
+The D_mat - R_ell graph is also modelled (the abstract and section 5 note
+that it can be modelled well): ln R_ell = a + b D_mat, fitted by least squares over the
+points with D_mat <= 1 (beyond that the longest rows reach the sweep's
+8192-entry clip and the graph flattens), with the D_mat where the model
+crosses c.
+
     python -m paper_2407_00019_amd.offline [--points 0,4,8] [--out FILE]
+    python -m paper_2407_00019_amd.offline --refit FILE   (models only, no GPU)
 
 Writes at_table.json next to this file by default and prints one JSON line
 per point.
@@ -131,6 +138,32 @@ def derive(p):
     return r
 
 
+def fit_rd(d, r, c=1.0, dmax=1.0):
+    """Least-squares fit of ln R = a + b D over the points with 0 <= D <= dmax
+    and R > 0.  Returns a, b, the root-mean-square residual in ln R, the
+    number of points used and d_cross = (ln c - a) / b, the D_mat where the
+    model's R_ell equals c (None unless b < 0)."""
+    pts = [(float(dd), float(rr)) for dd, rr in zip(d, r) if 0.0 <= dd <= dmax and rr > 0.0]
+    if len(pts) < 2:
+        return None
+    x = np.array([p[0] for p in pts])
+    y = np.log(np.array([p[1] for p in pts]))
+    b, a = np.polyfit(x, y, 1)
+    rms = float(np.sqrt(np.mean((y - (a + b * x)) ** 2)))
+    cross = (math.log(c) - a) / b if b < 0 else None
+    return {"a": float(a), "b": float(b), "rms_ln": rms, "points": len(pts), "d_max": dmax,
+            "d_cross": None if cross is None else float(cross)}
+
+
+def add_rd_models(table):
+    """Adds rd_model_vs_{base}_{family} for every stored graph."""
+    c = table.get("c", 1.0)
+    for key in [k for k in table if k.startswith("graph_vs_")]:
+        g = table[key]
+        table["rd_model" + key[len("graph"):]] = fit_rd([p[0] for p in g], [p[1] for p in g], c)
+    return table
+
+
 def launch_overhead_s():
     """Time of a CRS SpMV on a tiny matrix: the fixed cost of one launch."""
     import gen
@@ -163,7 +196,15 @@ def main(argv=None):
     ap.add_argument("--out", default=os.path.join(_HERE, "at_table.json"))
     ap.add_argument("--c", type=float, default=1.0)
     ap.add_argument("--families", default="scattered,local")
+    ap.add_argument("--refit", default=None, help="recompute the D-R models of an existing table and exit")
     a = ap.parse_args(argv)
+    if a.refit:
+        with open(a.refit) as f:
+            table = add_rd_models(json.load(f))
+        with open(a.refit, "w") as f:
+            json.dump(table, f, indent=1, default=float)
+        print(json.dumps({k: v for k, v in table.items() if k.startswith("rd_model")}), flush=True)
+        return
     idx = list(range(len(gen.DSWEEP_TARGETS))) if a.points == "all" else [int(s) for s in a.points.split(",")]
     dts = {"f64": spmvat.F64, "f32": spmvat.F32, "bf16": spmvat.BF16, "f16": spmvat.F16}
     dlist = [dts[s] for s in a.dtypes.split(",")]
@@ -264,6 +305,7 @@ def main(argv=None):
                 trans_bps[loc][f] = list(trans_bps[other][f])
     table["cost_model"] = {"spmv_bps": spmv_bps, "trans_bps": trans_bps, "launch_s": launch_s,
                            "local_band": spmvat.AT_LOCAL_BAND, "d_edges": list(spmvat.AT_DBUCKET_EDGES)}
+    add_rd_models(table)
     table["sweep"] = points
     with open(a.out, "w") as f:
         json.dump(table, f, indent=1, default=float)
