@@ -275,6 +275,40 @@ def dsweep_matrix(index: int, n: int = DSWEEP_N, local: bool = False) -> Crs:
     return m
 
 
+# Stand-ins for the paper's test matrices (section 4.2, Table 1): each has
+# the printed N, mean row length and D_mat (nnz follows from N and the mean,
+# within a few percent), columns uniform within 4096 of the diagonal (the
+# printed matrices are near-banded FEM and circuit matrices; their column
+# structure is not printed).  The lognormal log-sigma per matrix is the input
+# recipe written by tests/golden/make_table1_standins.py.
+TABLE1_WINDOW = 4096
+
+
+def table1_lengths(n: int, mean: float, s: float, seed: int) -> np.ndarray:
+    """Row lengths round(exp(ln mean - s^2/2 + s z_i)) clipped to [1, 8193]
+    and to the row's column window."""
+    lens = lognormal_lengths(n, mean, s, 1, min(n, 2 * TABLE1_WINDOW + 1), seed)
+    idx = np.arange(n)
+    room = np.minimum(idx + TABLE1_WINDOW, n - 1) - np.maximum(idx - TABLE1_WINDOW, 0) + 1
+    return np.minimum(lens, room).astype(np.int32)
+
+
+def table1_recipe() -> dict:
+    with open(os.path.join(_HERE, "table1_s.json")) as f:
+        return json.load(f)
+
+
+def table1_standin(no: int) -> Crs:
+    """Stand-in for Table 1 matrix number `no` (1..22)."""
+    tab = table1_recipe()
+    k = tab["no"].index(no)
+    n, mean, s = tab["n"][k], tab["mu"][k], tab["s"][k]
+    lens = table1_lengths(n, mean, s, seed_for(6, no))
+    m = window_rows(n, lens, TABLE1_WINDOW, seed_for(6, 100 + no))
+    m.name = f"table1_{no}_{tab['name'][k]}"
+    return m
+
+
 @dataclass
 class Job:
     """One SpMV job of the serving stream."""

@@ -23,6 +23,12 @@ crosses c.
 
     python -m paper_2407_00019_amd.offline [--points 0,4,8] [--out FILE]
     python -m paper_2407_00019_amd.offline --refit FILE   (models only, no GPU)
+    python -m paper_2407_00019_amd.offline --table1 [--out FILE]
+
+--table1 runs the same measurements on stand-ins for the paper's own 22
+test matrices (Table 1: the printed N, mean row length and D_mat; see
+gen.table1_standin) and writes their D_mat - R_ell graph, D* and model to
+table1_standins.json: an off-line phase shaped like the paper's.
 
 Writes at_table.json next to this file by default and prints one JSON line
 per point.
@@ -164,6 +170,35 @@ def add_rd_models(table):
     return table
 
 
+def table1_phase(out_path, c=1.0, reps=7):
+    """The off-line phase over the Table 1 stand-ins, binary64."""
+    import gen
+    tab = gen.table1_recipe()
+    rows = []
+    for k, no in enumerate(tab["no"]):
+        m = gen.table1_standin(no)
+        x = torch.from_numpy(gen.x_uniform(m.n, gen.seed_for(6, 200 + no)))
+        p = measure_point(m, spmvat.F64, x, reps)
+        p.update(derive(p))
+        rec = {"no": no, "name": tab["name"][k], "d_printed": tab["dmat_printed"][k],
+               "nnz_printed": tab["nnz_printed"][k]}
+        rec.update({kk: v for kk, v in p.items() if kk not in ("y", "bytes")})
+        rows.append(rec)
+        print(json.dumps(rec), flush=True)
+    res = {"c": c, "machine": torch.cuda.get_device_name(0), "matrices": rows}
+    for base in ("scalar", "best"):
+        d = [q["d_mat"] for q in rows]
+        r = [q[f"r_ell_{base}"] if q.get(f"r_ell_{base}") else 0.0 for q in rows]
+        feas = [1 if q["ell_feasible"] else 0 for q in rows]
+        t = spmvat.at_table_build(d, r, feas, c)
+        res[f"d_star_vs_{base}"] = t.d_star if math.isfinite(t.d_star) else "inf"
+        res[f"graph_vs_{base}"] = [[dd, rr, ff] for dd, rr, ff in zip(d, r, feas)]
+        res[f"rd_model_vs_{base}"] = fit_rd(d, r, c)
+    with open(out_path, "w") as f:
+        json.dump(res, f, indent=1, default=float)
+    print(json.dumps({k: v for k, v in res.items() if k.startswith(("d_star", "rd_model"))}), flush=True)
+
+
 def launch_overhead_s():
     """Time of a CRS SpMV on a tiny matrix: the fixed cost of one launch."""
     import gen
@@ -197,7 +232,12 @@ def main(argv=None):
     ap.add_argument("--c", type=float, default=1.0)
     ap.add_argument("--families", default="scattered,local")
     ap.add_argument("--refit", default=None, help="recompute the D-R models of an existing table and exit")
+    ap.add_argument("--table1", action="store_true", help="the off-line phase on the Table 1 stand-ins")
     a = ap.parse_args(argv)
+    if a.table1:
+        out = a.out if a.out != os.path.join(_HERE, "at_table.json") else os.path.join(_HERE, "table1_standins.json")
+        table1_phase(out, a.c, a.reps)
+        return
     if a.refit:
         with open(a.refit) as f:
             table = add_rd_models(json.load(f))
