@@ -206,9 +206,12 @@ spmv_status csr_to_ell(spmv_plan *p, int column_wise, const spmv_buffers *out,
  * variant (CRS only): 0 one thread per row (the plain CRS loop); 1 the
  * library's CRS kernel, currently the stream kernel; 2..7 a group of
  * 2^(variant-1) lanes per row; 8 the stream kernel (a workgroup stages the
- * products of 256 consecutive rows in LDS; each thread sums its own row in
- * storage order, the workgroup reduces rows of more than 256 entries).
- * Other formats take variant 0.
+ * products of 256/G consecutive rows in LDS and G lanes sum each row, G from
+ * the mean row length and n; with G = 1 a thread sums its row in storage
+ * order; the workgroup reduces rows of more than 256 entries).
+ * Other formats take variant 0; ELL_ROW splits a row's slots over several
+ * threads (the outer-parallel form of Fig. 4) when n is too small to fill
+ * the GPU with one thread per row.
  * Determinism: CRS, COO_ROW and ELL_ROW are deterministic run to run;
  * COO_COL and ELL_COL scatter with atomics and are not.  x and y must not
  * overlap.  SPMV_E_NOT_READY when the format has not been built. */
