@@ -390,7 +390,7 @@ SPMV_API spmv_status spmv_server_create(const spmv_server_config* cfg, spmv_serv
     s->slots.resize((size_t)cfg->slots);
     for (Slot& sl : s->slots) {
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&sl.event, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.event, hipEventDisableTiming | hipEventBlockingSync) != hipSuccess ||
             hipHostMalloc(reinterpret_cast<void**>(&sl.host_stats), sizeof(RowStats), hipHostMallocCoherent) != hipSuccess) {
             spmv_server_destroy(s);
             return SPMV_E_HIP;
