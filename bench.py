@@ -243,8 +243,8 @@ def main():
                     help="run one 1 GiB device copy first (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
-              "of this path is described in DESIGN.md, not run", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding this path "
+              "over several GPUs is designed but not built", file=sys.stderr)
         sys.exit(2)
 
     import torch
