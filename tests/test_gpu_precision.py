@@ -21,6 +21,9 @@ MATS = [
     ("stencil27_e20", lambda: gen.stencil27(20, 20, 20, 3)),
     ("rand_unsorted_dups", lambda: gen.random_small(4000, 9, 12, False, True, 0.2, integer_values=False)),
     ("powerlaw_small", lambda: gen.lognormal_matrix(60000, 16.0, 1.2, 11, 1, 3000)),
+    # odd n and n = 2 mod 4, next to the multiples of 4 above
+    ("rand_n3001", lambda: gen.random_small(3001, 12, 40, True, False, 0.1, integer_values=False)),
+    ("rand_n4002", lambda: gen.random_small(4002, 13, 40, False, False, 0.1, integer_values=False)),
 ]
 DTYPES = [(1, "f32"), (2, "bf16"), (3, "f16")]
 
