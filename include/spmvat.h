@@ -6,7 +6,9 @@
  * Conventions for every entry point
  *  - Matrices are square, n x n (section 2.1).  Indices are 0-based int32:
  *    the paper's 1-based IRP(1)=1 ... IRP(N+1)=NNZ+1 is irp[0]=0 ...
- *    irp[n]=nnz here.  1 <= n and 0 <= nnz <= INT32_MAX.
+ *    irp[n]=nnz here.  1 <= n and 0 <= nnz <= SPMV_MAX_NNZ = 2^31 - 2^20:
+ *    the kernels step through entry positions in 32-bit chunks of up to a
+ *    few thousand, and the 2^20 of headroom keeps every such step in range.
  *  - "device" pointers are HIP device memory of the current device; every
  *    device array must be 16-byte aligned (SPMV_E_ARG otherwise).
  *  - `stream` is a hipStream_t passed as void* (NULL: the default stream).
@@ -27,6 +29,8 @@
 
 #include <stddef.h>
 #include <stdint.h>
+
+#define SPMV_MAX_NNZ 2146435072   /* 2^31 - 2^20 */
 
 #ifdef __cplusplus
 extern "C" {

@@ -33,6 +33,7 @@ TORCH_OF_DTYPE = {v: k for k, v in DTYPE_OF_TORCH.items()}
 AT_DBUCKETS = 8
 AT_LOCAL_BAND = 65536
 AT_K_MARGIN = 1.1        # the k-aware rule's required predicted gain (spmvat.h)
+MAX_NNZ = 2**31 - 2**20  # SPMV_MAX_NNZ: headroom for the kernels' 32-bit position steps
 AT_DBUCKET_EDGES = (0.0625, 0.125, 0.25, 0.5, 1.0, 2.0, 4.0)
 
 

@@ -117,7 +117,7 @@ namespace spmvat {
 spmv_status plan_begin(spmv_plan* p, int32_t n, int64_t nnz, const int32_t* irp, const int32_t* icol,
                        const void* val, spmv_dtype val_type, void* plan_work, size_t plan_work_bytes,
                        RowStats* host_stats, hipStream_t s) {
-    if (n < 1 || nnz < 0 || nnz > INT32_MAX || !valid_dtype(val_type)) return SPMV_E_ARG;
+    if (n < 1 || nnz < 0 || nnz > SPMV_MAX_NNZ || !valid_dtype(val_type)) return SPMV_E_ARG;
     if (!irp || !plan_work || (nnz > 0 && (!icol || !val))) return SPMV_E_ARG;
     if (!aligned16(irp) || !aligned16(icol) || !aligned16(val) || !aligned16(plan_work)) return SPMV_E_ARG;
     if (plan_work_bytes < plan_ws_bytes(nnz)) return SPMV_E_ARG;
@@ -170,6 +170,8 @@ SPMV_API spmv_status spmv_plan_create(spmv_plan** plan, int32_t n, int64_t nnz, 
                                       void* plan_work, size_t plan_work_bytes, void* stream) {
     if (!plan) return SPMV_E_ARG;
     *plan = nullptr;
+    // sizes first: a rejected matrix touches neither the host heap nor HIP
+    if (n < 1 || nnz < 0 || nnz > SPMV_MAX_NNZ || !valid_dtype(val_type)) return SPMV_E_ARG;
     spmv_plan* p = new (std::nothrow) spmv_plan();
     if (!p) return SPMV_E_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);

@@ -410,7 +410,7 @@ SPMV_API spmv_status spmv_server_start(spmv_server* s) {
 }
 
 SPMV_API spmv_status spmv_server_submit(spmv_server* s, const spmv_job* job) {
-    if (!s || !job || job->n < 1 || job->nnz < 0 || job->nnz > INT32_MAX || job->k < 1 || job->shift < 0 ||
+    if (!s || !job || job->n < 1 || job->nnz < 0 || job->nnz > SPMV_MAX_NNZ || job->k < 1 || job->shift < 0 ||
         job->shift > 126 || !job->irp || !job->x0 || !job->y_out || (job->nnz > 0 && (!job->icol || !job->val)))
         return SPMV_E_ARG;
     spmv_job j = *job;

@@ -45,6 +45,23 @@ def test_status_strings():
     assert spmvat.status_string(99) == "unknown status"
 
 
+def test_plan_create_rejects_sizes_before_touching_the_gpu():
+    """n < 1, nnz < 0, nnz above SPMV_MAX_NNZ (2^31 - 2^20: headroom for the
+    kernels' 32-bit position steps) and an unknown value type are refused
+    with SPMV_E_ARG before any allocation, so this runs without a GPU."""
+    import ctypes
+    spmvat = _lib()
+    L = spmvat.lib()
+    with open(os.path.join(ROOT, "include", "spmvat.h")) as fh:
+        assert f"#define SPMV_MAX_NNZ {spmvat.MAX_NNZ}" in fh.read()
+    dummy = ctypes.c_void_p(16)   # never dereferenced: the sizes are checked first
+    for n, nnz, dt in ((0, 0, 0), (10, -1, 0), (10, spmvat.MAX_NNZ + 1, 0), (10, 2**31 - 1, 1), (10, 5, 7)):
+        h = ctypes.c_void_p()
+        s = L.spmv_plan_create(ctypes.byref(h), n, nnz, dummy, dummy, dummy, dt, dummy, 1 << 20, None)
+        assert s == spmvat.SPMV_E_ARG, (n, nnz, dt)
+        assert not h.value
+
+
 def test_workspace_size_grows_with_nnz():
     spmvat = _lib()
     a = spmvat.spmv_plan_workspace_bytes(10, 100)
