@@ -102,7 +102,7 @@ CcsGeom ccs_geom(int n) {
 
 // Per tile: entries per column block, into table[block * tiles + tile].
 __global__ void __launch_bounds__(kBlock)
-k_bucket_count(int n, int rows_per_tile, int tiles, int nb, int nb_bits, const int* __restrict__ irp,
+k_bucket_count(int n, int rows_per_tile, int tiles, int nb, const int* __restrict__ irp,
                const int* __restrict__ icol, int* __restrict__ table) {
     extern __shared__ int cnt[];   // nb
     const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
@@ -370,7 +370,7 @@ hipError_t run_bucketed(const CcsGeom& g, int n, int64_t nnz, const int* irp, co
                         int* table, int* csum, uint32_t* bkey, void* bval, int* ccp, int* irow_t, void* val_t,
                         ColSummary* sum, hipStream_t s) {
     hipLaunchKernelGGL(k_bucket_count, dim3(g.tiles), dim3(kBlock), g.nb * sizeof(int), s, n, g.rows, g.tiles,
-                       g.nb, g.nb_bits, irp, icol, table);
+                       g.nb, irp, icol, table);
     hipLaunchKernelGGL(k_table_reduce, dim3((unsigned)g.chunks), dim3(kBlock), 0, s, g.table, table, csum);
     hipLaunchKernelGGL(k_table_top, dim3(1), dim3(kBlock), 0, s, (int)g.chunks, csum, sum);
     hipLaunchKernelGGL(k_table_apply, dim3((unsigned)g.chunks), dim3(kBlock), 0, s, g.table, table, csum);
