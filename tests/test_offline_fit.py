@@ -50,3 +50,23 @@ def test_committed_models_cross_c_inside_the_measured_bracket():
         # first point sits at c within the timing noise
         assert last_pass < m["d_cross"] <= first_fail + 0.05, (key, last_pass, m["d_cross"], first_fail)
         assert m == fit_rd([p[0] for p in t[key]], [p[1] for p in t[key]], c)
+
+
+def test_derive_follows_eqs_1_to_3_for_both_crs_kernels():
+    """The off-line phase's SP, TT and R_ell (Eqs. (1)-(3)) against the
+    oracle's, for both CRS baselines; a point without an ELL-Row measurement
+    (refused by the memory guard) gets none."""
+    import oracle
+    from paper_2407_00019_amd.offline import derive
+    p = {"t_crs_scalar": 1.9, "t_crs_best": 0.14, "t_ell": 0.12, "t_trans_ell": 0.29}
+    r = derive(p)
+    for base in ("scalar", "best"):
+        sp = oracle.speedup(p[f"t_crs_{base}"], p["t_ell"])
+        tt = oracle.transform_cost(p["t_trans_ell"], p[f"t_crs_{base}"])
+        assert r[f"sp_{base}"] == sp and r[f"tt_{base}"] == tt and r[f"r_ell_{base}"] == oracle.r_ell(sp, tt)
+    # the worked example under Eq. (3): a 10x speedup bought with a
+    # transformation of 10 CRS SpMVs gives R = 1
+    r = derive({"t_crs_scalar": 1.0, "t_crs_best": 1.0, "t_ell": 0.1, "t_trans_ell": 10.0})
+    assert r["r_ell_best"] == pytest.approx(1.0)
+    r = derive({"t_crs_scalar": 1.0, "t_crs_best": 1.0})
+    assert r["sp_best"] is None and r["r_ell_scalar"] is None
