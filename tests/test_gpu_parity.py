@@ -217,6 +217,62 @@ def test_powerlaw_full_size():
     plan.close()
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("local", [False, True], ids=["scattered", "local"])
+def test_dsweep_d0_full_size(local):
+    """The D_mat-sweep shape at full size (n = 1,048,576, 32 entries per row,
+    D_mat = 0) in both column families, through every transformation and
+    SpMV the off-line phase times: arrays bit-exact, SpMV within 1e-13."""
+    m = gen.dsweep_matrix(0, local=local)
+    x = gen.x_uniform(m.n, gen.seed_for(5, 100))
+    g = run_gpu_all(m, x)
+    check_stats(m, g["stats"])
+    assert g["ell_w"] == 32
+    check_transforms(m, g, oracle_transforms(m))
+    yref = oracle.spmv_crs(m.n, m.irp, m.icol, m.val, x)
+    for key, y in g["y"].items():
+        assert oracle.rel_l2(y, yref) <= TOL64, (key, oracle.rel_l2(y, yref))
+
+
+@pytest.mark.slow
+def test_dsweep_d1_full_size_without_ell_row():
+    """A high-D_mat sweep matrix at full size (scattered columns, D_mat = 1):
+    ELL-Row is refused by the default memory guard; the statistics, COO-Row,
+    CCS, COO-Column and ELL-Column arrays are bit-exact and every SpMV that
+    can run is within 1e-13."""
+    import torch
+    spmvat = lib_ready()
+    m = gen.dsweep_matrix(8)
+    x = gen.x_uniform(m.n, gen.seed_for(5, 108))
+    irp, icol, val = to_dev(m)
+    xd = torch.from_numpy(x).to("cuda:0")
+    plan = spmvat.Plan(irp, icol, val)
+    check_stats(m, plan.stats)
+    assert abs(plan.stats.d_mat - 1.0) < 1e-4
+    s, _ = plan.sizes(spmvat.ELL_ROW)
+    assert s == spmvat.SPMV_E_TOO_LARGE
+    (irow,) = plan.to_coo()
+    ccp, irow_t, val_t = plan.to_ccs()
+    (jcol,) = plan.to_coo(column_wise=True)
+    (cv, cr), wc = plan.to_ell(column_wise=True)
+    # the oracle's arrays one by one (its ELL-Row would be ~1700 slots wide)
+    o_ccp, o_irow_t, o_val_t = oracle.csr_to_ccs(m.n, m.irp, m.icol, m.val)
+    assert np.array_equal(host(irow), oracle.csr_to_coo_row(m.n, m.irp))
+    assert np.array_equal(host(ccp), o_ccp)
+    assert np.array_equal(host(irow_t), o_irow_t)
+    assert np.array_equal(bits(host(val_t)), bits(o_val_t))
+    assert np.array_equal(host(jcol), oracle.ccs_to_coo_col(m.n, o_ccp))
+    o_cv, o_cr = oracle.to_ell(m.n, o_ccp, o_irow_t, o_val_t)
+    assert wc == oracle.max_len(m.n, o_ccp)
+    assert np.array_equal(bits(host(cv)), bits(o_cv)) and np.array_equal(host(cr), o_cr)
+    yref = oracle.spmv_crs(m.n, m.irp, m.icol, m.val, x)
+    for fmt, var in [(spmvat.CRS, 0), (spmvat.CRS, 1), (spmvat.CRS, 6), (spmvat.COO_ROW, 0),
+                     (spmvat.COO_COL, 0), (spmvat.ELL_COL, 0)]:
+        y = host(plan.spmv(fmt, xd, variant=var))
+        assert oracle.rel_l2(y, yref) <= TOL64, (fmt, var)
+    plan.close()
+
+
 def banded_with_long_column(n, seed):
     """Band of half-width 2 plus column 0 in every 8th row from row 8 on:
     column 0 then holds those rows and rows 0-2 of the band."""

@@ -24,6 +24,8 @@ MATS = [
     # odd n and n = 2 mod 4, next to the multiples of 4 above
     ("rand_n3001", lambda: gen.random_small(3001, 12, 40, True, False, 0.1, integer_values=False)),
     ("rand_n4002", lambda: gen.random_small(4002, 13, 40, False, False, 0.1, integer_values=False)),
+    # the D_mat-sweep shape at full size (n = 1,048,576, 32 per row, D_mat = 0)
+    ("dsweep_local_d0", lambda: gen.dsweep_matrix(0, local=True)),
 ]
 DTYPES = [(1, "f32"), (2, "bf16"), (3, "f16")]
 
