@@ -49,7 +49,8 @@ def _lib():
         lib.orc_u128_to_double.restype = f64
         lib.orc_dmat.argtypes = [i32, i64, i64, P, P, P]
         lib.orc_expand_ptr.argtypes = [i32, P, P]
-        lib.orc_csr_to_ccs.argtypes = [i32, P, P, P, ctypes.c_int, P, P, P, P]
+        lib.orc_csr_to_ccs.argtypes = [i32, P, P, P, ctypes.c_int, P, P, P]
+        lib.orc_csr_to_ccs.restype = ctypes.c_int
         lib.orc_max_len.argtypes = [i32, P]
         lib.orc_max_len.restype = i32
         lib.orc_to_ell.argtypes = [i32, P, P, P, ctypes.c_int, i32, P, P]
@@ -137,15 +138,16 @@ def csr_to_coo_row(n, irp):
 
 
 def csr_to_ccs(n, irp, icol, val):
-    """Phase I, CRS -> CCS: (ccp[n+1], irow_t[nnz], val_t[nnz])."""
+    """Phase I, CRS -> CCS: (ccp[n+1], irow_t[nnz], val_t[nnz]), entries of
+    a column by row, then by storage position within the row."""
     irp, icol = _i32(irp), _i32(icol)
     v, vb = _raw(val)
     nnz = icol.shape[0]
     ccp = np.empty(n + 1, np.int32)
     irow_t = np.empty(nnz, np.int32)
     val_t = np.empty(nnz, v.dtype)
-    cursor = np.empty(max(n, 1), np.int32)
-    _lib().orc_csr_to_ccs(n, _p(irp), _p(icol), _p(v), vb, _p(ccp), _p(irow_t), _p(val_t), _p(cursor))
+    if _lib().orc_csr_to_ccs(n, _p(irp), _p(icol), _p(v), vb, _p(ccp), _p(irow_t), _p(val_t)) != 0:
+        raise MemoryError("oracle CCS: out of host memory")
     return ccp, irow_t, val_t
 
 

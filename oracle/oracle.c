@@ -18,6 +18,7 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 /* ------------------------------------------------------------------ input */
@@ -123,34 +124,55 @@ void orc_expand_ptr(int32_t n, const int32_t *ptr, int32_t *idx)
 
 /* -------------------------------------------- CRS -> CCS, Phase I (sec 2.1)
  *
- * Counting sort of the nonzeros by column, following the paper's three
- * steps: count the nonzeros of every column; turn the counts into column
- * pointers by an exclusive prefix sum (ccp[n] = nnz); then walk the rows in
- * ascending order, each row's entries in storage order, and place every entry
- * at its column's cursor, advancing the cursor.  Row indices go to irow_t,
- * values to val_t.  The walk order makes the result stable: inside a column,
- * entries are ordered by row, and by storage position within a row.
+ * Written from what the column-wise form is, not from the loop that builds
+ * it.  CCS holds the same entries grouped by column: ccp[j] is the number of
+ * entries whose column is below j (so ccp[0] = 0 and ccp[n] = nnz), and the
+ * entries of column j fill positions ccp[j] .. ccp[j+1]-1 in the order the
+ * rows give them -- by row, and within a row by storage position, the order
+ * the paper's walk over the rows produces.  CRS position p grows with the
+ * row and with the place inside the row, so the key (icol[p], p) of every
+ * entry is distinct and sorting the keys ascending yields exactly that
+ * order; irow_t takes the row that owns each position and val_t its value.
  * Out-of-place: the CRS arrays are left untouched. */
-void orc_csr_to_ccs(int32_t n, const int32_t *irp, const int32_t *icol,
-                    const void *val, int vbytes,
-                    int32_t *ccp, int32_t *irow_t, void *val_t, int32_t *cursor)
+static int cmp_u64(const void *a, const void *b)
 {
-    for (int32_t j = 0; j < n; ++j) cursor[j] = 0;
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return (x > y) - (x < y);
+}
+
+int orc_csr_to_ccs(int32_t n, const int32_t *irp, const int32_t *icol,
+                   const void *val, int vbytes,
+                   int32_t *ccp, int32_t *irow_t, void *val_t)
+{
+    int64_t nnz = irp[n];
+    uint64_t *key = malloc(sizeof(uint64_t) * (size_t)(nnz > 0 ? nnz : 1));
+    int32_t *row_of = malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!key || !row_of) {
+        free(key);
+        free(row_of);
+        return -1;
+    }
     for (int32_t i = 0; i < n; ++i)
         for (int32_t p = irp[i]; p < irp[i + 1]; ++p)
-            cursor[icol[p]] += 1;
-    ccp[0] = 0;
-    for (int32_t j = 1; j <= n; ++j) ccp[j] = ccp[j - 1] + cursor[j - 1];
-    for (int32_t j = 0; j < n; ++j) cursor[j] = ccp[j];
+            row_of[p] = i;
+    for (int64_t p = 0; p < nnz; ++p)
+        key[p] = ((uint64_t)(uint32_t)icol[p] << 32) | (uint64_t)p;
+    qsort(key, (size_t)nnz, sizeof(uint64_t), cmp_u64);
     const unsigned char *v = (const unsigned char *)val;
     unsigned char *vt = (unsigned char *)val_t;
-    for (int32_t i = 0; i < n; ++i)
-        for (int32_t p = irp[i]; p < irp[i + 1]; ++p) {
-            int32_t q = cursor[icol[p]];
-            cursor[icol[p]] = q + 1;
-            irow_t[q] = i;
-            memcpy(vt + (size_t)q * vbytes, v + (size_t)p * vbytes, (size_t)vbytes);
-        }
+    for (int64_t q = 0; q < nnz; ++q) {
+        int64_t p = (int64_t)(key[q] & 0xffffffffu);
+        irow_t[q] = row_of[p];
+        memcpy(vt + (size_t)q * vbytes, v + (size_t)p * vbytes, (size_t)vbytes);
+    }
+    int64_t q = 0;
+    for (int32_t j = 0; j <= n; ++j) {
+        while (q < nnz && (int64_t)(key[q] >> 32) < j) ++q;
+        ccp[j] = (int32_t)q;
+    }
+    free(key);
+    free(row_of);
+    return 0;
 }
 
 /* ------------------------------------------------------ ELL, section 2.1

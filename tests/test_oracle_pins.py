@@ -80,6 +80,50 @@ def test_ccs_is_the_stable_sort_by_column(case):
     assert np.array_equal(np.diff(ccp), counts)
 
 
+def phase1_counting_sort(n, irp, icol, val):
+    """The three steps of section 2.1's Phase I in the paper's 1-based
+    indexing: count the entries of every column, prefix the counts into the
+    column pointer (its last element nnz + 1), then walk the rows in order
+    and drop each entry at its column's cursor."""
+    IRP = [0] + [int(v) + 1 for v in irp]       # IRP(1..n+1), 1-based
+    ICOL = [0] + [int(v) + 1 for v in icol]     # ICOL(1..nnz)
+    VAL = [0.0] + [float(v) for v in val]
+    nnz = IRP[n + 1] - 1
+    cnt = [0] * (n + 2)
+    for i in range(1, n + 1):
+        for j in range(IRP[i], IRP[i + 1]):
+            cnt[ICOL[j]] += 1
+    ptr = [0] * (n + 2)
+    ptr[1] = 1
+    for k in range(2, n + 2):
+        ptr[k] = ptr[k - 1] + cnt[k - 1]
+    cur = ptr[:]
+    irow_t = [0] * (nnz + 1)
+    val_t = [0.0] * (nnz + 1)
+    for i in range(1, n + 1):
+        for j in range(IRP[i], IRP[i + 1]):
+            k = cur[ICOL[j]]
+            cur[ICOL[j]] = k + 1
+            irow_t[k] = i
+            val_t[k] = VAL[j]
+    return (np.array(ptr[1:], np.int32) - 1, np.array(irow_t[1:], np.int32) - 1,
+            np.array(val_t[1:], np.float64))
+
+
+@pytest.mark.parametrize("case", SMALL_CASES)
+def test_ccs_equals_the_papers_counting_sort(case):
+    """The oracle builds CCS by sorting (column, position) keys; the paper's
+    Phase I builds it by counting and cursor placement.  Both must give the
+    same three arrays, bit for bit, also with unsorted rows and duplicates."""
+    n, seed, ml, srt, dup, ef = case
+    m = gen.random_small(n, seed, ml, srt, dup, ef, integer_values=False)
+    ccp, irow_t, val_t = oracle.csr_to_ccs(n, m.irp, m.icol, m.val)
+    p_ccp, p_irow, p_val = phase1_counting_sort(n, m.irp, m.icol, m.val)
+    assert np.array_equal(ccp, p_ccp)
+    assert np.array_equal(irow_t, p_irow)
+    assert np.array_equal(val_t.view(np.uint64), p_val.view(np.uint64))
+
+
 @pytest.mark.parametrize("case", [c for c in SMALL_CASES if not c[4]])
 def test_ccs_reads_back_as_the_transpose(case):
     n, seed, ml, srt, dup, ef = case
