@@ -158,6 +158,10 @@ spmv_status spmv_plan_create(spmv_plan **plan, int32_t n, int64_t nnz,
 /* Host only.  Copies the statistics out. */
 spmv_status spmv_plan_stats(const spmv_plan *p, spmv_stats *out);
 
+/* Host only.  The plan's value storage type (the val_type it was created
+ * with), which fixes the element type of x and y in spmv_exec. */
+spmv_status spmv_plan_value_type(const spmv_plan *p, spmv_dtype *out);
+
 /* Host only.  Largest number of bytes one transformed format (its output
  * arrays) may take; a transformation past it returns SPMV_E_TOO_LARGE
  * before any device work.  This is the memory guard of section 4.2, where

@@ -46,6 +46,16 @@ class SpmvError(RuntimeError):
         super().__init__(msg)
 
 
+class SpmvArgError(SpmvError, ValueError):
+    """An argument the binding refuses before calling the library: a tensor
+    that is not on the GPU, not contiguous, of the wrong element type or too
+    short for what the call will read or write (status SPMV_E_ARG)."""
+
+    def __init__(self, what: str, detail: str):
+        self.status = SPMV_E_ARG
+        ValueError.__init__(self, f"{what}: invalid argument: {detail}")
+
+
 class spmv_stats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("sum_len", ctypes.c_int64),
                 ("sum_len2", ctypes.c_int64), ("max_row", ctypes.c_int32), ("min_row", ctypes.c_int32),
@@ -113,6 +123,8 @@ def lib():
         L.spmv_plan_create.restype = st
         L.spmv_plan_stats.argtypes = [P, ctypes.POINTER(spmv_stats)]
         L.spmv_plan_stats.restype = st
+        L.spmv_plan_value_type.argtypes = [P, ctypes.POINTER(ctypes.c_int)]
+        L.spmv_plan_value_type.restype = st
         L.spmv_plan_set_limit.argtypes = [P, sz]
         L.spmv_plan_set_limit.restype = st
         L.spmv_buffer_sizes.argtypes = [P, ctypes.c_int, ctypes.POINTER(spmv_sizes)]
@@ -196,13 +208,49 @@ def _check(status: int, what: str, plan=None) -> None:
         raise SpmvError(status, what, detail)
 
 
+def _dev(t, what: str, name: str, dtype=None, numel: int = 0, device=None):
+    """Checks that t (a torch tensor handed to the library as a device
+    pointer) lives on the GPU, is contiguous, has element type `dtype` (when
+    given) and holds at least `numel` elements.  Raw integer addresses pass
+    unchecked: they are the C ABI's own contract.  Marshalling only."""
+    if t is None or isinstance(t, int):
+        return
+    if not isinstance(t, torch.Tensor):
+        raise SpmvArgError(what, f"{name} must be a torch tensor, not {type(t).__name__}")
+    if not t.is_cuda:
+        raise SpmvArgError(what, f"{name} must be a GPU tensor (it is on {t.device})")
+    if device is not None and t.device != device:
+        raise SpmvArgError(what, f"{name} is on {t.device}, the other arrays on {device}")
+    if not t.is_contiguous():
+        raise SpmvArgError(what, f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise SpmvArgError(what, f"{name} must be {dtype}, not {t.dtype}")
+    if t.numel() < numel:
+        raise SpmvArgError(what, f"{name} holds {t.numel()} elements, needs at least {numel}")
+
+
+def _overlap(a, b) -> bool:
+    """Whether the storage of two tensors overlaps (both on the GPU)."""
+    if not isinstance(a, torch.Tensor) or not isinstance(b, torch.Tensor) or a.numel() == 0 or b.numel() == 0:
+        return False
+    a0, b0 = a.data_ptr(), b.data_ptr()
+    return a0 < b0 + b.numel() * b.element_size() and b0 < a0 + a.numel() * a.element_size()
+
+
+def vector_dtype(val_type: int) -> torch.dtype:
+    """Element type of x and y for a plan whose values are stored as
+    val_type: binary64 with binary64 values, else binary32."""
+    return torch.float64 if val_type == F64 else torch.float32
+
+
 def status_string(s: int) -> str:
     return lib().spmv_status_string(s).decode()
 
 
-def _buffers(tensors) -> spmv_buffers:
+def _buffers(tensors, what: str = "buffers") -> spmv_buffers:
     b = spmv_buffers()
     for k, t in enumerate(tensors):
+        _dev(t, what, f"out[{k}]")
         b.ptr[k] = _ptr(t).value
         b.bytes[k] = t.numel() * t.element_size()
     return b
@@ -215,6 +263,14 @@ def spmv_plan_workspace_bytes(n: int, nnz: int) -> int:
 
 
 def spmv_plan_create(n, nnz, irp, icol, val, val_type, plan_work, stream=None) -> ctypes.c_void_p:
+    w = "spmv_plan_create"
+    if val_type not in TORCH_OF_DTYPE:
+        raise SpmvArgError(w, f"unknown value type {val_type}")
+    dev = irp.device if isinstance(irp, torch.Tensor) else None
+    _dev(irp, w, "irp", torch.int32, n + 1)
+    _dev(icol, w, "icol", torch.int32, nnz, dev)
+    _dev(val, w, "val", TORCH_OF_DTYPE[val_type], nnz, dev)
+    _dev(plan_work, w, "plan_work", None, 0, dev)
     h = ctypes.c_void_p()
     s = lib().spmv_plan_create(ctypes.byref(h), n, nnz, _ptr(irp), _ptr(icol), _ptr(val), val_type,
                                _ptr(plan_work), plan_work.numel() * plan_work.element_size(), _stream(stream))
@@ -240,24 +296,41 @@ def spmv_buffer_sizes(plan, fmt: int):
 
 
 def csr_to_coo(plan, column_wise: int, out, work=None, stream=None) -> None:
-    b = _buffers(out)
+    b = _buffers(out, "csr_to_coo")
+    _dev(work, "csr_to_coo", "work")
     wb = 0 if work is None else work.numel() * work.element_size()
     _check(lib().csr_to_coo(plan, column_wise, ctypes.byref(b), _ptr(work), wb, _stream(stream)), "csr_to_coo", plan)
 
 
 def csr_to_ccs(plan, out, work, stream=None) -> None:
-    b = _buffers(out)
+    b = _buffers(out, "csr_to_ccs")
+    _dev(work, "csr_to_ccs", "work")
     wb = work.numel() * work.element_size()
     _check(lib().csr_to_ccs(plan, ctypes.byref(b), _ptr(work), wb, _stream(stream)), "csr_to_ccs", plan)
 
 
 def csr_to_ell(plan, column_wise: int, out, work=None, stream=None) -> None:
-    b = _buffers(out)
+    b = _buffers(out, "csr_to_ell")
+    _dev(work, "csr_to_ell", "work")
     wb = 0 if work is None else work.numel() * work.element_size()
     _check(lib().csr_to_ell(plan, column_wise, ctypes.byref(b), _ptr(work), wb, _stream(stream)), "csr_to_ell", plan)
 
 
+def spmv_plan_value_type(plan) -> int:
+    out = ctypes.c_int()
+    _check(lib().spmv_plan_value_type(plan, ctypes.byref(out)), "spmv_plan_value_type")
+    return out.value
+
+
 def spmv_exec(plan, fmt: int, variant: int, x, y, stream=None) -> None:
+    if isinstance(x, torch.Tensor) or isinstance(y, torch.Tensor):
+        w = "spmv_exec"
+        n = spmv_plan_stats(plan).n
+        vt = vector_dtype(spmv_plan_value_type(plan))
+        _dev(x, w, "x", vt, n)
+        _dev(y, w, "y", vt, n, x.device if isinstance(x, torch.Tensor) else None)
+        if _overlap(x, y):
+            raise SpmvArgError(w, "x and y must not overlap")
     _check(lib().spmv_exec(plan, fmt, variant, _ptr(x), _ptr(y), _stream(stream)), "spmv_exec", plan)
 
 
@@ -290,6 +363,11 @@ def at_choose_format_stats(stats: spmv_stats, val_type: int, max_format_bytes: i
 
 
 def spmv_convert_values(inp, out, to: int, stream=None) -> None:
+    w = "spmv_convert_values"
+    if to not in (F32, BF16, F16):
+        raise SpmvArgError(w, f"target type must be F32, BF16 or F16, not {to}")
+    _dev(inp, w, "in", torch.float64)
+    _dev(out, w, "out", TORCH_OF_DTYPE[to], inp.numel(), inp.device)
     _check(lib().spmv_convert_values(_ptr(inp), _ptr(out), inp.numel(), to, _stream(stream)), "spmv_convert_values")
 
 
@@ -361,7 +439,11 @@ class Plan:
     format built on it (torch tensors, kept alive with the plan)."""
 
     def __init__(self, irp: torch.Tensor, icol: torch.Tensor, val: torch.Tensor, stream=None):
-        assert irp.dtype == torch.int32 and icol.dtype == torch.int32
+        if val.dtype not in DTYPE_OF_TORCH:
+            raise SpmvArgError("Plan", f"val must be float64, float32, bfloat16 or float16, not {val.dtype}")
+        _dev(irp, "Plan", "irp", torch.int32, 1)
+        _dev(icol, "Plan", "icol", torch.int32, 0, irp.device)
+        _dev(val, "Plan", "val", val.dtype, icol.numel(), irp.device)
         self.n = irp.numel() - 1
         self.nnz = icol.numel()
         self.dtype = DTYPE_OF_TORCH[val.dtype]

@@ -197,6 +197,12 @@ SPMV_API spmv_status spmv_plan_stats(const spmv_plan* p, spmv_stats* out) {
     return SPMV_OK;
 }
 
+SPMV_API spmv_status spmv_plan_value_type(const spmv_plan* p, spmv_dtype* out) {
+    if (!p || !out) return SPMV_E_ARG;
+    *out = p->dt;
+    return SPMV_OK;
+}
+
 SPMV_API spmv_status spmv_plan_set_limit(spmv_plan* p, size_t max_format_bytes) {
     if (!p) return SPMV_E_ARG;
     p->limit = max_format_bytes;

@@ -517,3 +517,117 @@ def test_ell_row_outer_parallel_every_split(parts, width):
         else:
             assert oracle.rel_l2(y, yref) <= TOL64, parts
         plan.close()
+
+
+def _integer_copy(m, seed):
+    """The same sparsity pattern with small-integer values, so every partial
+    sum of an SpMV is exact."""
+    v = np.random.default_rng(seed).integers(-4, 5, m.nnz).astype(np.float64)
+    return gen.Crs(m.n, m.irp, m.icol, v, m.name + "_int")
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("local", [False, True], ids=["scattered", "local"])
+def test_dsweep_wide_ell_row_full_size(local):
+    """The D_mat-sweep point D = 0.125 at full size (n = 1,048,576): binary64
+    ELL-Row rows wider than the unrolled kernels cover (Fig. 3 with the slot
+    loop taken at run time, two rows per thread), the kernel the off-line
+    phase times there.  ELL arrays bit-exact with the oracle; SpMV within
+    1e-13 of the oracle's Fig. 3 loop, and bitwise on small-integer data."""
+    import torch
+    spmvat = lib_ready()
+    m = gen.dsweep_matrix(1, local=local)
+    w_o = oracle.max_len(m.n, m.irp)
+    # the launch rule takes one thread per row (n fills the GPU), two rows
+    # per thread (n even) and the run-time slot loop (width > 32)
+    assert m.n % 2 == 0 and w_o > 32 and _ell_parts(m.n, w_o) == 1
+    x = gen.x_uniform(m.n, gen.seed_for(5, 201))
+    xi = np.round(x * 3)
+    for mm, xx, exact in ((m, x, False), (_integer_copy(m, 77), xi, True)):
+        irp, icol, val = to_dev(mm)
+        xd = torch.from_numpy(xx).to("cuda:0")
+        plan = spmvat.Plan(irp, icol, val)
+        check_stats(mm, plan.stats)
+        (ev, ec), w = plan.to_ell()
+        assert w == w_o
+        o_ev, o_ec = oracle.csr_to_ell_row(mm.n, mm.irp, mm.icol, mm.val)
+        assert np.array_equal(bits(host(ev)), bits(o_ev))
+        assert np.array_equal(host(ec), o_ec)
+        y = host(plan.spmv(spmvat.ELL_ROW, xd))
+        yref = oracle.spmv_ell_row(mm.n, w, o_ev, o_ec, xx)
+        if exact:
+            assert np.array_equal(y, yref)
+        else:
+            assert oracle.rel_l2(y, yref) <= TOL64
+        del o_ev, o_ec
+        plan.close()
+
+
+def dup_long_column(n, reps, seed):
+    """Every row holds column 7 `reps` times (duplicates, kept as separate
+    entries) plus 0-3 random columns, rows unsorted: column 7 then holds
+    reps * n entries, more than n and than a workgroup's sort."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for i in range(n):
+        c = [7] * reps + rng.integers(0, n, size=int(rng.integers(0, 4))).tolist()
+        rng.shuffle(c)
+        rows.append(c)
+    lens = np.array([len(r) for r in rows])
+    irp = np.zeros(n + 1, np.int64)
+    irp[1:] = np.cumsum(lens)
+    icol = np.concatenate([np.array(r, np.int32) for r in rows])
+    return gen.Crs(n, irp.astype(np.int32), icol, rng.standard_normal(icol.shape[0]), f"dup_long_{n}x{reps}")
+
+
+@pytest.mark.parametrize("n,reps", [(3000, 3), (9000, 2)])
+def test_ccs_duplicate_column_longer_than_n(n, reps):
+    """A column with more entries than the matrix has rows (only possible
+    with duplicates) and than one workgroup sorts: CCS, COO-Column and
+    ELL-Column bit-exact with the oracle, the duplicates in row, then
+    storage order; SpMV within 1e-13."""
+    import torch
+    spmvat = lib_ready()
+    m = dup_long_column(n, reps, 300 + n)
+    assert oracle.validate_crs(m.n, m.irp, m.icol) == 0
+    x = gen.x_uniform(n, 12)
+    g = run_gpu_all(m, x)
+    o = oracle_transforms(m)
+    assert g["max_col"] >= reps * n > max(n, 8192)
+    check_transforms(m, g, o)
+    yref = oracle.spmv_crs(m.n, m.irp, m.icol, m.val, x)
+    for key, y in g["y"].items():
+        assert oracle.rel_l2(y, yref) <= TOL64, (key, oracle.rel_l2(y, yref))
+
+
+def test_binding_refuses_vectors_that_do_not_fit_the_plan():
+    """x and y of the wrong element type, too short, on the host, strided or
+    overlapping are refused by the binding before any kernel runs, and the
+    plan stays usable."""
+    import torch
+    spmvat = lib_ready()
+    m = gen.laplace_64x64()
+    irp, icol, val = to_dev(m)
+    plan = spmvat.Plan(irp, icol, val)
+    dev = irp.device
+    x = torch.from_numpy(gen.x_uniform(m.n, 3)).to(dev)
+    bad = [
+        (x.float(), torch.empty_like(x)),                           # binary32 x on a binary64 plan
+        (x, torch.empty(m.n - 1, dtype=torch.float64, device=dev)),  # short y
+        (x.cpu(), torch.empty_like(x)),                             # host x
+        (torch.empty(2 * m.n, dtype=torch.float64, device=dev)[::2], torch.empty_like(x)),  # strided
+        (x, x),                                                     # x and y overlap
+    ]
+    for xx, yy in bad:
+        with pytest.raises(spmvat.SpmvArgError):
+            spmvat.spmv_exec(plan.handle, spmvat.CRS, 1, xx, yy)
+    yref = oracle.spmv_crs(m.n, m.irp, m.icol, m.val, host(x))
+    assert oracle.rel_l2(host(plan.spmv(spmvat.CRS, x, variant=1)), yref) <= TOL64
+    # a plan over reduced-precision values takes binary32 vectors
+    p32 = spmvat.Plan(irp, icol, spmvat.convert_values(val, spmvat.F32))
+    with pytest.raises(spmvat.SpmvArgError):
+        p32.spmv(spmvat.CRS, x)
+    y32 = host(p32.spmv(spmvat.CRS, x.float(), variant=1))
+    assert np.all(np.isfinite(y32))
+    p32.close()
+    plan.close()
