@@ -226,6 +226,27 @@ spmv_status csr_to_ell(spmv_plan *p, int column_wise, const spmv_buffers *out,
 spmv_status spmv_exec(const spmv_plan *p, spmv_format f, int variant,
                       const void *x, void *y, void *stream);
 
+/* COO-Row SpMV that allocates nothing, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  No plan and no workspace: the
+ * per-workgroup carries of the segmented reduction live in a fixed device
+ * array of 1 MiB that the library holds on every GPU it runs on until the
+ * process ends.  y = A x with A in COO-Row form: irow[nnz] (non-decreasing,
+ * as csr_to_coo writes it), icol[nnz], val[nnz] of type val_type, x[n] and
+ * y[n] as for spmv_exec; all device arrays, 16-byte aligned.  y is cleared
+ * by a kernel and then written by the same kernels as
+ * spmv_exec(COO_ROW), so the result is bitwise the same.
+ * Errors: SPMV_E_ARG for n < 1, nnz < 0, an unknown type, a null or
+ * misaligned array; SPMV_E_TOO_LARGE for nnz > SPMV_COO_ROW_NOALLOC_MAX_NNZ
+ * (nothing is enqueued in either case); SPMV_E_HIP if a launch fails.
+ * Indices are not checked: every irow and icol entry must lie in [0, n).
+ * Calls that overlap in time on one GPU (two streams, or two host threads)
+ * share the array and race; successive calls on one stream do not. */
+#define SPMV_COO_ROW_NOALLOC_MAX_NNZ 134217728   /* 65,536 workgroups of 2048 entries */
+spmv_status spmv_exec_coo_row_noalloc(int32_t n, int64_t nnz, const int32_t *irow, const int32_t *icol,
+                                      const void *val, spmv_dtype val_type, const void *x, void *y,
+                                      void *stream);
+
 /* ---------------------------------------------------------- auto-tuning */
 
 /* Host only.  Off-line phase step (4) of section 2.2: from m benchmark points

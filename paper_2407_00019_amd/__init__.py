@@ -137,6 +137,8 @@ def lib():
         L.csr_to_ccs.restype = st
         L.spmv_exec.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, P]
         L.spmv_exec.restype = st
+        L.spmv_exec_coo_row_noalloc.argtypes = [i32, i64, P, P, P, ctypes.c_int, P, P, P]
+        L.spmv_exec_coo_row_noalloc.restype = st
         L.at_table_build.argtypes = [P, P, P, i32, f64, ctypes.POINTER(at_table)]
         L.at_table_build.restype = st
         L.at_choose_format.argtypes = [P, ctypes.POINTER(at_table), i64, ctypes.POINTER(ctypes.c_int),
@@ -332,6 +334,28 @@ def spmv_exec(plan, fmt: int, variant: int, x, y, stream=None) -> None:
         if _overlap(x, y):
             raise SpmvArgError(w, "x and y must not overlap")
     _check(lib().spmv_exec(plan, fmt, variant, _ptr(x), _ptr(y), _stream(stream)), "spmv_exec", plan)
+
+
+COO_ROW_NOALLOC_MAX_NNZ = 134217728   # SPMV_COO_ROW_NOALLOC_MAX_NNZ
+
+
+def spmv_exec_coo_row_noalloc(n: int, nnz: int, irow, icol, val, val_type: int, x, y, stream=None) -> None:
+    """y = A x in COO-Row form with no plan and no workspace (the library's
+    fixed per-device array holds the carries).  Same checks as spmv_exec."""
+    w = "spmv_exec_coo_row_noalloc"
+    if val_type not in TORCH_OF_DTYPE:
+        raise SpmvArgError(w, f"unknown value type {val_type}")
+    dev = x.device if isinstance(x, torch.Tensor) else None
+    _dev(irow, w, "irow", torch.int32, nnz, dev)
+    _dev(icol, w, "icol", torch.int32, nnz, dev)
+    _dev(val, w, "val", TORCH_OF_DTYPE[val_type], nnz, dev)
+    vt = vector_dtype(val_type)
+    _dev(x, w, "x", vt, n)
+    _dev(y, w, "y", vt, n, dev)
+    if _overlap(x, y):
+        raise SpmvArgError(w, "x and y must not overlap")
+    _check(lib().spmv_exec_coo_row_noalloc(n, nnz, _ptr(irow), _ptr(icol), _ptr(val), val_type, _ptr(x), _ptr(y),
+                                           _stream(stream)), w)
 
 
 def at_table_build(d, r, feasible=None, c: float = 1.0) -> at_table:

@@ -446,6 +446,19 @@ SPMV_API spmv_status spmv_exec(const spmv_plan* p, spmv_format f, int variant, c
     return plan_exec(p, f, variant, x, y, 1.0, static_cast<hipStream_t>(stream));
 }
 
+SPMV_API spmv_status spmv_exec_coo_row_noalloc(int32_t n, int64_t nnz, const int32_t* irow, const int32_t* icol,
+                                               const void* val, spmv_dtype val_type, const void* x, void* y,
+                                               void* stream) {
+    if (n < 1 || nnz < 0 || !valid_dtype(val_type)) return SPMV_E_ARG;
+    if (nnz > SPMV_COO_ROW_NOALLOC_MAX_NNZ) return SPMV_E_TOO_LARGE;
+    if (!x || !y || !aligned16(x) || !aligned16(y)) return SPMV_E_ARG;
+    if (nnz > 0 && (!irow || !icol || !val || !aligned16(irow) || !aligned16(icol) || !aligned16(val)))
+        return SPMV_E_ARG;
+    const hipError_t e = launch_spmv_coo_row_static((int)val_type, n, nnz, irow, icol, val, x, y,
+                                                    static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SPMV_OK : SPMV_E_HIP;
+}
+
 // ----------------------------------------------------------- conversion
 
 SPMV_API spmv_status spmv_convert_values(const double* in, void* out, int64_t m, spmv_dtype to, void* stream) {

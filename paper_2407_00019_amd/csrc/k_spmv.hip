@@ -22,6 +22,9 @@
 //                 kernel in workgroup order -- deterministic.
 //  COO-Column     Fig. 1: chunks of entries in column order; inside a
 //                 chunk one lane per column, y(row) += ... with atomics.
+#include <mutex>
+
+#include "../../include/spmvat.h"
 #include "common.h"
 #include "kernels.h"
 
@@ -621,6 +624,51 @@ hipError_t launch_spmv_coo_row(int dtype, int n, int64_t nnz, const int* irow, c
                            (const Carry<X>*)carries, (X*)y);
     });
     return hipGetLastError();
+}
+
+// ------------------------------------------ COO-Row SpMV without allocation
+// The same two kernels as the plan path, with the per-workgroup carries in a
+// fixed device array instead of the plan workspace.  Every GPU that runs it
+// holds its own copy of the array; its address is looked up once per device
+// (the array's name is not a device address in host code).
+
+namespace {
+constexpr size_t kScratchBytes = 1u << 20;   // carries of up to 65,536 workgroups
+static_assert(sizeof(Carry<double>) == 16 && sizeof(Carry<float>) <= 16, "carry record size");
+constexpr int64_t kScratchMaxNnz = (int64_t)(kScratchBytes / sizeof(Carry<double>)) * kCooTile;
+static_assert(kScratchMaxNnz == SPMV_COO_ROW_NOALLOC_MAX_NNZ, "the header states the limit");
+constexpr int kScratchDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices];
+
+// Address of this device's copy of `scratch`, or null on failure.
+void* scratch_on_current_device() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+int64_t coo_row_static_max_nnz() { return kScratchMaxNnz; }
+
+hipError_t launch_spmv_coo_row_static(int dtype, int n, int64_t nnz, const int* irow, const int* icol,
+                                      const void* val, const void* x, void* y, hipStream_t s) {
+    void* carries = scratch_on_current_device();
+    if (!carries) return hipErrorInvalidSymbol;
+    // rows without entries get no store from the kernels: clear y first
+    // (a fill kernel, so the call can be captured in a graph)
+    hipError_t e = launch_fill_zero(y, (int64_t)n * (dtype == 0 ? 8 : 4), s);
+    if (e != hipSuccess) return e;
+    return launch_spmv_coo_row(dtype, n, nnz, irow, icol, val, x, y, carries, s);
 }
 
 }  // namespace spmvat

@@ -104,6 +104,11 @@ hipError_t launch_spmv_coo_row(int dtype, int n, int64_t nnz, const int* irow, c
 hipError_t launch_spmv_coo_col(int dtype, int64_t nnz, const int* jcol, const int* irow_t,
                                const void* val_t, const void* x, void* y, hipStream_t s);
 size_t coo_carry_bytes(int64_t nnz);
+// COO-Row SpMV with its carries in a fixed per-device array (no workspace):
+// y is cleared first, then the same kernels as launch_spmv_coo_row run.
+int64_t coo_row_static_max_nnz();
+hipError_t launch_spmv_coo_row_static(int dtype, int n, int64_t nnz, const int* irow, const int* icol,
+                                      const void* val, const void* x, void* y, hipStream_t s);
 
 // ---- value conversion (to: 1 F32, 2 BF16, 3 F16)
 hipError_t launch_convert(int to, int64_t m, const double* in, void* out, hipStream_t s);

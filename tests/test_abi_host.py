@@ -262,3 +262,20 @@ def test_arena_first_fit_and_coalescing():
         L.spmv_arena_free(A, o, b)
     assert L.spmv_arena_free_bytes(A) == cap and L.spmv_arena_largest(A) == cap
     L.spmv_arena_destroy(A)
+
+
+def test_noalloc_coo_row_refuses_before_touching_the_gpu():
+    """The COO-Row entry point that allocates nothing checks its sizes before
+    any HIP call: n < 1 and an unknown type give SPMV_E_ARG, nnz past the
+    fixed carry array gives SPMV_E_TOO_LARGE (the header states the limit)."""
+    import ctypes
+    spmvat = _lib()
+    L = spmvat.lib()
+    with open(os.path.join(ROOT, "include", "spmvat.h")) as fh:
+        assert f"#define SPMV_COO_ROW_NOALLOC_MAX_NNZ {spmvat.COO_ROW_NOALLOC_MAX_NNZ}" in fh.read()
+    d = ctypes.c_void_p(256)   # never dereferenced: the sizes are checked first
+    f = L.spmv_exec_coo_row_noalloc
+    assert f(0, 0, d, d, d, spmvat.F64, d, d, None) == spmvat.SPMV_E_ARG
+    assert f(8, -1, d, d, d, spmvat.F64, d, d, None) == spmvat.SPMV_E_ARG
+    assert f(8, 8, d, d, d, 7, d, d, None) == spmvat.SPMV_E_ARG
+    assert f(8, spmvat.COO_ROW_NOALLOC_MAX_NNZ + 1, d, d, d, spmvat.F32, d, d, None) == spmvat.SPMV_E_TOO_LARGE
