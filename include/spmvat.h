@@ -109,9 +109,10 @@ typedef struct {
 #define AT_DBUCKETS 8
 #define AT_LOCAL_BAND 65536
 /* The k-aware rule transforms only when the estimated cost with the
- * transformation, times AT_K_MARGIN, stays below the cost of staying in
- * CRS: the model's per-job estimates err by about ten percent (measured over
- * the serving stream), so a smaller predicted gain is not acted on. */
+ * transformation, times a margin m, stays below the cost of staying in CRS:
+ * a predicted gain smaller than the model's typical error is not acted on.
+ * m is the table's k_margin, measured by the off-line phase on the
+ * machine; AT_K_MARGIN applies when the table carries none (0). */
 #define AT_K_MARGIN 1.1
 typedef struct {
     double c;                                 /* R_ell threshold (the paper uses 1.0) */
@@ -120,6 +121,7 @@ typedef struct {
     double spmv_bps[2][6][2][AT_DBUCKETS];    /* [locality][format][variant][bucket] SpMV rate */
     double trans_bps[2][6][AT_DBUCKETS];      /* [locality][format][bucket] transformation rate */
     double launch_s;                          /* fixed cost added per kernel launch */
+    double k_margin;                          /* the k-aware rule's margin; 0: AT_K_MARGIN */
 } at_table;
 
 typedef struct {
@@ -130,7 +132,7 @@ typedef struct {
     double t_fmt_hat;      /* estimated SpMV seconds in the chosen format */
     double t_trans_hat;    /* estimated transformation seconds into it */
     double k_break_even;   /* TT / (1 - 1/SP) for the chosen format (where its cost
-                            * equals CRS's, before AT_K_MARGIN); 0 for CRS */
+                            * equals CRS's, before the margin); 0 for CRS */
 } at_decision;
 
 /* ------------------------------------------------------------- planning */
@@ -168,6 +170,25 @@ spmv_status spmv_plan_value_type(const spmv_plan *p, spmv_dtype *out);
  * ELL overflowed memory for torso1. */
 spmv_status spmv_plan_set_limit(spmv_plan *p, size_t max_format_bytes);
 
+/* Algorithms of the CRS -> CCS transformation (Phase I of section 2.1).
+ * All give the same arrays bit for bit; they differ in speed by structure.
+ *   AUTO      chosen from the bandwidth and n (the default)
+ *   SORT      column counts, a scatter of (position, row) keys through
+ *             per-column cursors, then a per-column sort of the keys
+ *   BUCKETED  two-level stable counting sort over all 1024-column blocks
+ *             (n <= 2^22)
+ *   BANDED    two-level stable counting sort over the 128-column blocks of
+ *             each row tile's column window (limited bandwidth) */
+typedef enum {
+    SPMV_CCS_AUTO = 0, SPMV_CCS_SORT = 1, SPMV_CCS_BUCKETED = 2, SPMV_CCS_BANDED = 3
+} spmv_ccs_algorithm;
+
+/* Host only.  Selects the algorithm csr_to_ccs (and spmv_buffer_sizes for
+ * CCS) uses from now on.  SPMV_E_ARG for an unknown value or one that does
+ * not apply to the matrix (BUCKETED with n > 2^22; BANDED when a row
+ * tile's column window is too wide or n > 2^25). */
+spmv_status spmv_plan_set_ccs_algorithm(spmv_plan *p, spmv_ccs_algorithm alg);
+
 /* Host only.  Output and workspace sizes of the transformation into `f`
  * (COO_ROW, CCS, COO_COL, ELL_ROW, ELL_COL).  ELL_COL needs csr_to_ccs to
  * have run (its width is the longest column): SPMV_E_NOT_READY before.
@@ -196,6 +217,22 @@ spmv_status csr_to_coo(spmv_plan *p, int column_wise, const spmv_buffers *out,
  * longest column. */
 spmv_status csr_to_ccs(spmv_plan *p, const spmv_buffers *out, void *work, size_t work_bytes,
                        void *stream);
+
+/* In-place CRS -> CCS: Phase I of section 2.1 with its final copy-back.
+ * The CCS arrays are built in `work` (as csr_to_ccs builds them, bit-exact)
+ * and then copied over the CRS arrays: the column pointers (n + 1) over
+ * irp, the row numbers (nnz) over icol, the values (nnz) over val.  irp,
+ * icol and val must be the arrays the plan was created with (SPMV_E_ARG
+ * otherwise), handed back writable.  Afterwards the plan's CCS lives in
+ * those arrays and its CRS is gone: COO-Column and ELL-Column can be built
+ * and run from it; CRS SpMV, COO-Row, ELL-Row conversion and another CCS
+ * give SPMV_E_NOT_READY (an ELL-Row built before is its own copy and stays
+ * usable).  work: device scratch of spmv_ccs_inplace_workspace_bytes, only
+ * during the call.  The memory guard does not apply: the result replaces
+ * the CRS arrays.  Synchronises `stream` as csr_to_ccs does. */
+spmv_status spmv_ccs_inplace_workspace_bytes(const spmv_plan *p, size_t *bytes);
+spmv_status csr_to_ccs_inplace(spmv_plan *p, int32_t *irp, int32_t *icol, void *val,
+                               void *work, size_t work_bytes, void *stream);
 
 /* CRS -> ELL (section 2.1).  column_wise = 0: ELL-Row from the CRS rows,
  * width = longest row.  column_wise = 1: ELL-Column from the CCS columns
@@ -261,7 +298,7 @@ spmv_status at_table_build(const double *d, const double *r, const int32_t *feas
  * rule, ELL_ROW when D_mat < D* and ELL-Row fits the plan's limit, else
  * CRS (variant 1, the library's CRS kernel, which D* is measured against).  k_repeats > 0 and a calibrated table: the option with
  * the least estimated transformation + k_repeats SpMVs among COO_ROW and
- * ELL_ROW (when it fits), if AT_K_MARGIN times that cost is below
+ * ELL_ROW (when it fits), if the margin times that cost is below
  * k_repeats SpMVs of the faster CRS variant; otherwise CRS. */
 spmv_status at_choose_format(const spmv_plan *p, const at_table *t, int64_t k_repeats,
                              spmv_format *fmt, int *variant, at_decision *why);
@@ -293,22 +330,28 @@ const char *spmv_plan_last_error(const spmv_plan *p);
  * iteration counts after the on-line phase).  Binary32 values, x and y.
  *
  * Jobs become visible at their arrival time and wait in FIFO order.  A job
- * is admitted when one of `slots` HIP streams is free and its CRS footprint
- * fits in the server's device arena (one allocation of hbm_cap bytes made
- * at creation).  Its statistics are computed and read back asynchronously;
- * then the format is chosen (policy 0: at_choose_format_stats with k = the
- * job's k; policy 1: CRS variant 1), allocated only if it fits right now
- * (else the job stays in CRS), built, and the chain
+ * is admitted when one of `slots` ingest streams is free and its CRS and
+ * vector footprint fits in the server's device arena (one allocation of
+ * hbm_cap bytes made at creation).  The slot copies it in, computes its
+ * statistics, chooses the format (policy 0 and 2: at_choose_format_stats
+ * with k = the job's k, among CRS and ELL-Row; policy 1: CRS), allocates
+ * the converted format only if it fits right now (else the job stays in
+ * CRS) and converts; under policy 2 a converted job then gives its CRS
+ * arrays back to the arena (the memory policy that the transformation's
+ * extra footprint calls for), so more jobs fit at once.  Every prepared job
+ * joins the running batch: each batched launch advances the chain
  *     y_1 = A x_0,  x_t = 2^-shift y_t,  y_{t+1} = A x_t   (t < k)
- * runs on the slot's stream; y_k is copied to y_out.  Jobs on different
- * slots overlap on the device.  Host arrays must stay valid until the job is
- * reported; pinned host memory lets the copies run asynchronously. */
+ * of every running job by one SpMV, each in its own format, and jobs join
+ * and leave between launches; y_k is copied to y_out.  A job's result does
+ * not depend on the jobs beside it.  Host arrays must stay valid until the
+ * job is reported; pinned host memory lets the copies run asynchronously. */
 
 typedef struct spmv_server spmv_server;
 
 typedef struct {
-    int32_t slots;       /* jobs in flight at once, one HIP stream each, 1..64 */
-    int32_t policy;      /* 0: per-job k-aware choice, 1: always CRS (variant 1) */
+    int32_t slots;       /* jobs being copied in and prepared at once, one HIP stream each, 1..64 */
+    int32_t policy;      /* 0: per-job k-aware choice, 1: always CRS, 2: as 0, and a converted
+                          *    job gives back its CRS arrays */
     size_t hbm_cap;      /* device bytes the server owns */
     at_table table;      /* auto-tuning table for policy 0 */
 } spmv_server_config;

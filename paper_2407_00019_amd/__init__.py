@@ -25,6 +25,7 @@ _LIB = None
 # enums of spmvat.h
 SPMV_OK, SPMV_E_ARG, SPMV_E_MATRIX, SPMV_E_TOO_LARGE, SPMV_E_NOT_READY, SPMV_E_HIP = range(6)
 CRS, COO_ROW, CCS, COO_COL, ELL_ROW, ELL_COL = range(6)
+CCS_AUTO, CCS_SORT, CCS_BUCKETED, CCS_BANDED = range(4)   # spmv_ccs_algorithm
 F64, F32, BF16, F16 = range(4)
 FORMAT_NAMES = {CRS: "crs", COO_ROW: "coo_row", CCS: "ccs", COO_COL: "coo_col", ELL_ROW: "ell_row",
                 ELL_COL: "ell_col"}
@@ -75,7 +76,8 @@ class spmv_buffers(ctypes.Structure):
 class at_table(ctypes.Structure):
     _fields_ = [("c", ctypes.c_double), ("d_star", ctypes.c_double), ("calibrated", ctypes.c_int32),
                 ("spmv_bps", (((ctypes.c_double * AT_DBUCKETS) * 2) * 6) * 2),
-                ("trans_bps", ((ctypes.c_double * AT_DBUCKETS) * 6) * 2), ("launch_s", ctypes.c_double)]
+                ("trans_bps", ((ctypes.c_double * AT_DBUCKETS) * 6) * 2), ("launch_s", ctypes.c_double),
+                ("k_margin", ctypes.c_double)]
 
 
 class spmv_server_config(ctypes.Structure):
@@ -127,6 +129,8 @@ def lib():
         L.spmv_plan_value_type.restype = st
         L.spmv_plan_set_limit.argtypes = [P, sz]
         L.spmv_plan_set_limit.restype = st
+        L.spmv_plan_set_ccs_algorithm.argtypes = [P, ctypes.c_int]
+        L.spmv_plan_set_ccs_algorithm.restype = st
         L.spmv_buffer_sizes.argtypes = [P, ctypes.c_int, ctypes.POINTER(spmv_sizes)]
         L.spmv_buffer_sizes.restype = st
         for name in ("csr_to_coo", "csr_to_ell"):
@@ -135,6 +139,10 @@ def lib():
             fn.restype = st
         L.csr_to_ccs.argtypes = [P, ctypes.POINTER(spmv_buffers), P, sz, P]
         L.csr_to_ccs.restype = st
+        L.spmv_ccs_inplace_workspace_bytes.argtypes = [P, ctypes.POINTER(sz)]
+        L.spmv_ccs_inplace_workspace_bytes.restype = st
+        L.csr_to_ccs_inplace.argtypes = [P, P, P, P, P, sz, P]
+        L.csr_to_ccs_inplace.restype = st
         L.spmv_exec.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, P]
         L.spmv_exec.restype = st
         L.spmv_exec_coo_row_noalloc.argtypes = [i32, i64, P, P, P, ctypes.c_int, P, P, P]
@@ -290,6 +298,10 @@ def spmv_plan_set_limit(plan, max_format_bytes: int) -> None:
     _check(lib().spmv_plan_set_limit(plan, max_format_bytes), "spmv_plan_set_limit")
 
 
+def spmv_plan_set_ccs_algorithm(plan, alg: int) -> None:
+    _check(lib().spmv_plan_set_ccs_algorithm(plan, alg), "spmv_plan_set_ccs_algorithm")
+
+
 def spmv_buffer_sizes(plan, fmt: int):
     """(status, spmv_sizes): sizes are filled even for SPMV_E_TOO_LARGE."""
     out = spmv_sizes()
@@ -309,6 +321,23 @@ def csr_to_ccs(plan, out, work, stream=None) -> None:
     _dev(work, "csr_to_ccs", "work")
     wb = work.numel() * work.element_size()
     _check(lib().csr_to_ccs(plan, ctypes.byref(b), _ptr(work), wb, _stream(stream)), "csr_to_ccs", plan)
+
+
+def spmv_ccs_inplace_workspace_bytes(plan) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().spmv_ccs_inplace_workspace_bytes(plan, ctypes.byref(out)), "spmv_ccs_inplace_workspace_bytes")
+    return out.value
+
+
+def csr_to_ccs_inplace(plan, irp, icol, val, work, stream=None) -> None:
+    w = "csr_to_ccs_inplace"
+    _dev(irp, w, "irp", torch.int32)
+    _dev(icol, w, "icol", torch.int32)
+    _dev(val, w, "val")
+    _dev(work, w, "work")
+    wb = work.numel() * work.element_size()
+    _check(lib().csr_to_ccs_inplace(plan, _ptr(irp), _ptr(icol), _ptr(val), _ptr(work), wb, _stream(stream)), w,
+           plan)
 
 
 def csr_to_ell(plan, column_wise: int, out, work=None, stream=None) -> None:
@@ -448,7 +477,28 @@ def at_table_from_json(d: dict) -> at_table:
                 for b_, val in enumerate(buckets):
                     t.trans_bps[loc][int(f_)][b_] = val
         t.launch_s = cm.get("launch_s", 0.0)
+    t.k_margin = float(d.get("k_margin", 0.0) or 0.0)
     return t
+
+
+def kernel_source_sha() -> str:
+    """Hash of the kernel sources (csrc/*.hip, *.h): a table or profile
+    measured with other kernels carries another value."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(_HERE, "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def table_matches_kernels(d: dict):
+    """Whether an off-line table (its JSON) was measured with the kernels of
+    this tree: True / False, or None when the table carries no stamp."""
+    sha = d.get("kernel_source_sha")
+    return None if sha is None else sha == kernel_source_sha()
 
 
 def convert_values(val64: torch.Tensor, to: int, stream=None) -> torch.Tensor:
@@ -522,7 +572,9 @@ class Plan:
         self.buffers[fmt] = out
         return out
 
-    def to_ccs(self, stream=None):
+    def to_ccs(self, stream=None, algorithm: int | None = None):
+        if algorithm is not None:
+            spmv_plan_set_ccs_algorithm(self.handle, algorithm)
         out, work, _ = self._alloc(CCS)
         csr_to_ccs(self.handle, out, work, stream)
         self.buffers[CCS] = out
@@ -530,6 +582,20 @@ class Plan:
         for f in (COO_COL, ELL_COL):
             self.buffers.pop(f, None)
         return out
+
+    def to_ccs_inplace(self, stream=None):
+        """CCS over the plan's own CRS tensors (the copy-back of Phase I):
+        afterwards irp, icol and val hold the column pointers, row numbers
+        and values, and CRS-based calls return SPMV_E_NOT_READY."""
+        irp, icol, val = self.crs
+        work = torch.empty(max(spmv_ccs_inplace_workspace_bytes(self.handle), 16), dtype=torch.uint8,
+                           device=self.device)
+        csr_to_ccs_inplace(self.handle, irp, icol, val, work, stream)
+        for f in (COO_ROW, CCS, COO_COL, ELL_COL):
+            self.buffers.pop(f, None)
+        self.buffers[CCS] = [irp, icol, val]
+        self.inplace_work = work    # kept until the stream has used it
+        return irp, icol, val
 
     def to_ell(self, column_wise: bool = False, stream=None):
         fmt = ELL_COL if column_wise else ELL_ROW

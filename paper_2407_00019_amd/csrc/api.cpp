@@ -2,10 +2,12 @@
 // dispatch and the auto-tuner's host-side decisions (section 2.2).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -54,24 +56,39 @@ size_t crs_bytes(const spmv_plan* p) {
     return (size_t)(p->n + 1) * 4 + (size_t)p->nnz * (4 + (size_t)vbytes_of(p->dt));
 }
 
-// CRS -> CCS algorithm by the matrix's structure: scattered columns (the
-// bandwidth too wide for the LDS-privatised window) with n <= 2^22 take the
-// two-level counting sort; everything else column counts, a scatter and
-// per-column sorts (privatised in LDS when the window fits).
-bool ccs_bucketed(int32_t n, int32_t bw) { return n <= (1 << kCcsRowBits) && !ccs_privatised(bw); }
+// CRS -> CCS algorithm (spmv_ccs_algorithm).  Chosen by the matrix's
+// structure unless the plan names one:
+//  - limited bandwidth (a row tile's window of 128-column blocks fits the
+//    kernels' LDS): the banded two-level counting sort;
+//  - else scattered columns with n <= 2^22: the two-level counting sort
+//    over all column blocks;
+//  - else column counts, a scatter of keys and per-column sorts.
+bool ccs_banded_ok(int32_t n, int32_t bw, int32_t max_row) { return wccs_geom(n, bw, max_row).usable; }
+bool ccs_bucketed_ok(int32_t n) { return n <= (1 << kCcsRowBits); }
+
+int ccs_route(int32_t n, int32_t bw, int32_t max_row, int alg) {
+    if (alg != SPMV_CCS_AUTO) return alg;
+    if (ccs_banded_ok(n, bw, max_row)) return SPMV_CCS_BANDED;
+    if (ccs_bucketed_ok(n) && !ccs_privatised(bw)) return SPMV_CCS_BUCKETED;
+    return SPMV_CCS_SORT;
+}
 
 // CCS workspace layout: bucketed -- count table, its chunk sums, summary,
 // level-1 keys and values; else -- counts/cursors, scan sums and maxima,
-// long-column lists, summary, keys, merge scratch.
+// long-column lists and their extents, summary, the windowed route's flags,
+// then one region holding either the windowed route's bitmaps and count
+// table or the sort route's keys and merge scratch.
 struct CcsWs {
-    size_t cursor, bsum, mid, lng, sum, keys, tmp;   // per-column sort path
-    size_t table, csum, bkey, bval;                  // bucketed path
+    size_t cursor, bsum, mid, lng, ext, sum, info, keys, tmp;   // sort and windowed routes
+    size_t wtable, bstart, wkey, wval;                        // windowed route (overlays keys)
+    size_t table, csum, bkey, bval;                           // bucketed route
     size_t total;
 };
-CcsWs ccs_ws(int32_t n, int64_t nnz, int vb, int32_t bw) {
+CcsWs ccs_ws(int32_t n, int64_t nnz, int vb, int32_t bw, int32_t max_row, int alg) {
     CcsWs w{};
     size_t o = 0;
-    if (ccs_bucketed(n, bw)) {
+    const int route = ccs_route(n, bw, max_row, alg);
+    if (route == SPMV_CCS_BUCKETED) {
         const CcsGeom g = ccs_geom(n);
         w.table = o; o += round_up((size_t)g.table * 4, kAlign);
         w.csum = o;  o += round_up((size_t)g.chunks * 4, kAlign);
@@ -87,11 +104,51 @@ CcsWs ccs_ws(int32_t n, int64_t nnz, int vb, int32_t bw) {
     const size_t nlong = std::min<size_t>((size_t)n, (size_t)(nnz / (kSortMid + 1)) + 1);
     w.mid = o;    o += round_up(nmid * 4, kAlign);
     w.lng = o;    o += round_up(nlong * 4, kAlign);
+    w.ext = o;    o += round_up(nlong * 8, kAlign);
     w.sum = o;    o += round_up(sizeof(ColSummary), kAlign);
-    w.keys = o;   o += round_up((size_t)nnz * 8, kAlign);
-    w.tmp = o;    o += round_up((size_t)std::min<int64_t>(n, nnz) * 8, kAlign);
+    w.info = o;   o += round_up(sizeof(WccsInfo), kAlign);
+    w.keys = o;
+    const size_t sort_bytes = round_up((size_t)nnz * 8, kAlign) + round_up((size_t)std::min<int64_t>(n, nnz) * 8, kAlign);
+    w.tmp = o + round_up((size_t)nnz * 8, kAlign);
+    size_t win_bytes = 0;
+    if (route == SPMV_CCS_BANDED) {
+        const WccsGeom g = wccs_geom(n, bw, max_row);
+        size_t q = o;
+        w.wtable = q; q += round_up((size_t)g.table * 4, kAlign);
+        w.bstart = q; q += round_up(((size_t)g.nb + 1) * 4, kAlign);
+        w.wkey = q;   q += round_up((size_t)nnz * 4, kAlign);
+        w.wval = q;   q += round_up((size_t)nnz * vb, kAlign);
+        win_bytes = q - o;
+    }
+    o += std::max(sort_bytes, win_bytes);
     w.total = o;
     return w;
+}
+
+// Pinned host records for the row statistics of spmv_plan_create: taken
+// for the call and returned after it, so their number is the most calls
+// that ever ran at once, whatever threads made them.
+std::mutex g_pinned_mu;
+std::vector<RowStats*> g_pinned_free;
+
+RowStats* pinned_take() {
+    {
+        std::lock_guard<std::mutex> g(g_pinned_mu);
+        if (!g_pinned_free.empty()) {
+            RowStats* r = g_pinned_free.back();
+            g_pinned_free.pop_back();
+            return r;
+        }
+    }
+    RowStats* r = nullptr;
+    if (hipHostMalloc(reinterpret_cast<void**>(&r), sizeof(RowStats), hipHostMallocCoherent) != hipSuccess)
+        return nullptr;
+    return r;
+}
+
+void pinned_give(RowStats* r) {
+    std::lock_guard<std::mutex> g(g_pinned_mu);
+    g_pinned_free.push_back(r);
 }
 
 bool check_buffers(const spmv_buffers* out, int count, const spmv_sizes& need) {
@@ -175,17 +232,18 @@ SPMV_API spmv_status spmv_plan_create(spmv_plan** plan, int32_t n, int64_t nnz, 
     spmv_plan* p = new (std::nothrow) spmv_plan();
     if (!p) return SPMV_E_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    // one pinned buffer per calling thread receives the statistics (kept
-    // for the life of the thread; plans on different threads do not share it)
-    thread_local RowStats* pinned = nullptr;
-    if (!pinned && hipHostMalloc(reinterpret_cast<void**>(&pinned), sizeof(RowStats), hipHostMallocCoherent) != hipSuccess) {
-        pinned = nullptr;
+    // a pinned record receives the statistics straight from the kernel
+    RowStats* pinned = pinned_take();
+    if (!pinned) {
         delete p;
         return SPMV_E_HIP;
     }
     spmv_status st = plan_begin(p, n, nnz, irp, icol, val, val_type, plan_work, plan_work_bytes, pinned, s);
     if (st == SPMV_OK && hipStreamSynchronize(s) != hipSuccess) st = SPMV_E_HIP;
     if (st == SPMV_OK) st = plan_finish(p, *pinned);
+    // the record goes back only once nothing on the stream can still write it
+    if (st == SPMV_E_HIP) (void)hipStreamSynchronize(s);
+    pinned_give(pinned);
     if (st != SPMV_OK) { delete p; return st; }
     *plan = p;
     return SPMV_OK;
@@ -206,6 +264,25 @@ SPMV_API spmv_status spmv_plan_value_type(const spmv_plan* p, spmv_dtype* out) {
 SPMV_API spmv_status spmv_plan_set_limit(spmv_plan* p, size_t max_format_bytes) {
     if (!p) return SPMV_E_ARG;
     p->limit = max_format_bytes;
+    return SPMV_OK;
+}
+
+SPMV_API spmv_status spmv_plan_set_ccs_algorithm(spmv_plan* p, spmv_ccs_algorithm alg) {
+    if (!p) return SPMV_E_ARG;
+    switch (alg) {
+        case SPMV_CCS_AUTO:
+        case SPMV_CCS_SORT:
+            break;
+        case SPMV_CCS_BUCKETED:
+            if (!ccs_bucketed_ok(p->n)) return SPMV_E_ARG;
+            break;
+        case SPMV_CCS_BANDED:
+            if (!ccs_banded_ok(p->n, p->st.bandwidth, p->st.max_row)) return SPMV_E_ARG;
+            break;
+        default:
+            return SPMV_E_ARG;
+    }
+    p->ccs_alg = alg;
     return SPMV_OK;
 }
 
@@ -239,7 +316,7 @@ SPMV_API spmv_status spmv_buffer_sizes(const spmv_plan* p, spmv_format f, spmv_s
             out->bytes[0] = (n + 1) * 4;
             out->bytes[1] = nnz * 4;
             out->bytes[2] = nnz * vb;
-            out->workspace = ccs_ws(p->n, p->nnz, vbytes_of(p->dt), p->st.bandwidth).total;
+            out->workspace = ccs_ws(p->n, p->nnz, vbytes_of(p->dt), p->st.bandwidth, p->st.max_row, p->ccs_alg).total;
             return SPMV_OK;
         case SPMV_COO_COL:
             out->bytes[0] = nnz * 4;
@@ -267,6 +344,7 @@ SPMV_API spmv_status csr_to_coo(spmv_plan* p, int column_wise, const spmv_buffer
                                 size_t work_bytes, void* stream) {
     (void)work; (void)work_bytes;
     if (!p) return SPMV_E_ARG;
+    if (!column_wise && p->crs_consumed) return SPMV_E_NOT_READY;
     spmv_sizes need;
     spmv_status st = spmv_buffer_sizes(p, column_wise ? SPMV_COO_COL : SPMV_COO_ROW, &need);
     if (st != SPMV_OK) return st;
@@ -284,6 +362,7 @@ SPMV_API spmv_status csr_to_coo(spmv_plan* p, int column_wise, const spmv_buffer
 SPMV_API spmv_status csr_to_ccs(spmv_plan* p, const spmv_buffers* out, void* work, size_t work_bytes,
                                 void* stream) {
     if (!p) return SPMV_E_ARG;
+    if (p->crs_consumed) return SPMV_E_NOT_READY;
     spmv_sizes need;
     spmv_status st = spmv_buffer_sizes(p, SPMV_CCS, &need);
     if (st != SPMV_OK) return st;
@@ -292,15 +371,24 @@ SPMV_API spmv_status csr_to_ccs(spmv_plan* p, const spmv_buffers* out, void* wor
     if (!work || !aligned16(work) || work_bytes < need.workspace) return SPMV_E_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int vb = vbytes_of(p->dt);
-    const CcsWs w = ccs_ws(p->n, p->nnz, vb, p->st.bandwidth);
+    const int32_t bw = p->st.bandwidth, mr = p->st.max_row;
+    const int route = ccs_route(p->n, bw, mr, p->ccs_alg);
+    const CcsWs w = ccs_ws(p->n, p->nnz, vb, bw, mr, p->ccs_alg);
     char* base = static_cast<char*>(work);
     int32_t* ccp = static_cast<int32_t*>(out->ptr[0]);
     int32_t* irow_t = static_cast<int32_t*>(out->ptr[1]);
     void* val_t = out->ptr[2];
     ColSummary* dsum = reinterpret_cast<ColSummary*>(base + w.sum);
     ColSummary cs{};
+    auto built = [&]() {
+        p->ccp = ccp; p->irow_t = irow_t; p->val_t = val_t; p->has_ccs = true;
+        p->st.max_col = cs.max_len;
+        p->jcol = nullptr; p->has_coo_col = false;   // a rebuilt CCS invalidates the formats built on it
+        p->ellc_w = -1; p->ellc_val = nullptr; p->ellc_row = nullptr;
+        return SPMV_OK;
+    };
 
-    if (ccs_bucketed(p->n, p->st.bandwidth)) {
+    if (route == SPMV_CCS_BUCKETED) {
         // level 1 (count table, its scan, ordered distribution to column
         // blocks) and level 2 (ordered placement inside each block); one sync
         // at the end for the longest column
@@ -316,19 +404,44 @@ SPMV_API spmv_status csr_to_ccs(spmv_plan* p, const spmv_buffers* out, void* wor
             p->err = "column-block counts do not add up to nnz";
             return SPMV_E_HIP;
         }
-        p->ccp = ccp; p->irow_t = irow_t; p->val_t = val_t; p->has_ccs = true;
-        p->st.max_col = cs.max_len;
-        p->jcol = nullptr; p->has_coo_col = false;   // a rebuilt CCS invalidates the formats built on it
-        p->ellc_w = -1; p->ellc_val = nullptr; p->ellc_row = nullptr;
-        return SPMV_OK;
+        return built();
     }
     int32_t* cursor = reinterpret_cast<int32_t*>(base + w.cursor);
     int32_t* bsum = reinterpret_cast<int32_t*>(base + w.bsum);
     int32_t* mid = reinterpret_cast<int32_t*>(base + w.mid);
     int32_t* lng = reinterpret_cast<int32_t*>(base + w.lng);
+    int32_t* ext = reinterpret_cast<int32_t*>(base + w.ext);
     unsigned long long* keys = reinterpret_cast<unsigned long long*>(base + w.keys);
     unsigned long long* tmp = reinterpret_cast<unsigned long long*>(base + w.tmp);
 
+    if (p->nnz > 0 && route == SPMV_CCS_BANDED) {
+        // (1) per-(tile, wave) counts over the window blocks, per-block walk
+        // -> block lengths, scan -> block starts, (2) ordered distribution to
+        // the blocks, per-block placement; one sync at the end
+        const WccsGeom g = wccs_geom(p->n, bw, mr);
+        int32_t* table = reinterpret_cast<int32_t*>(base + w.wtable);
+        int32_t* bstart = reinterpret_cast<int32_t*>(base + w.bstart);
+        WccsInfo* dinfo = reinterpret_cast<WccsInfo*>(base + w.info);
+        WccsInfo wi{};
+        HIP_TRY(p, launch_wccs_front(g, p->n, bw, p->irp, p->icol, table, cursor, dinfo, s));
+        HIP_TRY(p, launch_col_scan(g.nb, cursor, bstart, cursor, bsum, nullptr, nullptr, dsum, s));
+        HIP_TRY(p, launch_wccs_back(g, p->n, bw, vb, p->irp, p->icol, p->val, table, bstart,
+                                    reinterpret_cast<uint32_t*>(base + w.wkey), base + w.wval, ccp, irow_t, val_t,
+                                    dinfo, s));
+        HIP_TRY(p, hipMemcpyAsync(&cs, dsum, sizeof(cs), hipMemcpyDeviceToHost, s));
+        HIP_TRY(p, hipMemcpyAsync(&wi, dinfo, sizeof(wi), hipMemcpyDeviceToHost, s));
+        HIP_TRY(p, hipStreamSynchronize(s));
+        if (wi.flags & kWccsOutside) {
+            p->err = "a column index lies outside the bandwidth measured when the plan was made";
+            return SPMV_E_MATRIX;
+        }
+        if ((int64_t)cs.total != p->nnz) {
+            p->err = "column counts do not add up to nnz";
+            return SPMV_E_HIP;
+        }
+        cs.max_len = wi.kmax;
+        return built();
+    }
     // (1) column counts, (2) exclusive scan -> ccp and cursors
     HIP_TRY(p, hipMemsetAsync(cursor, 0, (size_t)p->n * 4, s));
     if (p->nnz > 0) HIP_TRY(p, launch_col_count(p->n, p->st.bandwidth, p->irp, p->icol, cursor, s));
@@ -345,26 +458,87 @@ SPMV_API spmv_status csr_to_ccs(spmv_plan* p, const spmv_buffers* out, void* wor
         HIP_TRY(p, launch_ccs_sort_small(p->n, ccp, keys, p->val, vb, irow_t, val_t, s));
         HIP_TRY(p, launch_ccs_sort_mid(cs.n_mid, mid, ccp, keys, p->val, vb, irow_t, val_t, s));
         if (cs.n_long > 0) {
-            std::vector<int32_t> cols((size_t)cs.n_long);
-            HIP_TRY(p, hipMemcpyAsync(cols.data(), lng, cols.size() * 4, hipMemcpyDeviceToHost, s));
+            // every long column's (start, end) in one copy
+            std::vector<int32_t> se((size_t)cs.n_long * 2);
+            HIP_TRY(p, launch_col_extents(cs.n_long, lng, ccp, ext, s));
+            HIP_TRY(p, hipMemcpyAsync(se.data(), ext, se.size() * 4, hipMemcpyDeviceToHost, s));
             HIP_TRY(p, hipStreamSynchronize(s));
-            for (int32_t j : cols) {
-                int32_t se[2];
-                HIP_TRY(p, hipMemcpyAsync(se, ccp + j, 8, hipMemcpyDeviceToHost, s));
-                HIP_TRY(p, hipStreamSynchronize(s));
-                const int32_t len = se[1] - se[0];
+            for (int32_t i = 0; i < cs.n_long; ++i) {
+                const int32_t start = se[2 * (size_t)i], len = se[2 * (size_t)i + 1] - start;
                 // the merge passes need len keys of scratch; longer columns (only
                 // possible with duplicate entries) rank without scratch
                 const size_t cap = (size_t)std::min<int64_t>(p->n, p->nnz);
-                HIP_TRY(p, launch_ccs_sort_long(se[0], len, keys, (size_t)len <= cap ? tmp : nullptr, p->val, vb,
+                HIP_TRY(p, launch_ccs_sort_long(start, len, keys, (size_t)len <= cap ? tmp : nullptr, p->val, vb,
                                                 irow_t, val_t, s));
             }
         }
     }
-    p->ccp = ccp; p->irow_t = irow_t; p->val_t = val_t; p->has_ccs = true;
-    p->st.max_col = cs.max_len;
-    p->jcol = nullptr; p->has_coo_col = false;   // a rebuilt CCS invalidates the formats built on it
-    p->ellc_w = -1; p->ellc_val = nullptr; p->ellc_row = nullptr;
+    return built();
+}
+
+// Temporary CCS arrays at the front of the in-place workspace, then the
+// workspace of csr_to_ccs.
+namespace {
+struct InplaceWs {
+    size_t ccp, irow, val, ccs_work, ccs_work_bytes, total;
+};
+InplaceWs inplace_ws(const spmv_plan* p) {
+    InplaceWs w{};
+    spmv_sizes sz{};
+    (void)spmv_buffer_sizes(p, SPMV_CCS, &sz);
+    size_t o = 0;
+    w.ccp = o;  o += round_up(sz.bytes[0], kAlign);
+    w.irow = o; o += round_up(std::max<size_t>(sz.bytes[1], 1), kAlign);
+    w.val = o;  o += round_up(std::max<size_t>(sz.bytes[2], 1), kAlign);
+    w.ccs_work = o;
+    w.ccs_work_bytes = sz.workspace;
+    o += round_up(sz.workspace, kAlign);
+    w.total = o;
+    return w;
+}
+}  // namespace
+
+SPMV_API spmv_status spmv_ccs_inplace_workspace_bytes(const spmv_plan* p, size_t* bytes) {
+    if (!p || !bytes) return SPMV_E_ARG;
+    *bytes = inplace_ws(p).total;
+    return SPMV_OK;
+}
+
+SPMV_API spmv_status csr_to_ccs_inplace(spmv_plan* p, int32_t* irp, int32_t* icol, void* val, void* work,
+                                        size_t work_bytes, void* stream) {
+    if (!p) return SPMV_E_ARG;
+    if (p->crs_consumed) return SPMV_E_NOT_READY;
+    // the caller hands back, writable, the very arrays the plan borrowed
+    if (irp != p->irp || icol != p->icol || val != p->val) return SPMV_E_ARG;
+    const InplaceWs w = inplace_ws(p);
+    if (!work || !aligned16(work) || work_bytes < w.total) return SPMV_E_ARG;
+    spmv_sizes need{};
+    spmv_status st = spmv_buffer_sizes(p, SPMV_CCS, &need);
+    if (st != SPMV_OK) return st;
+    char* base = static_cast<char*>(work);
+    spmv_buffers tmp{};
+    for (int k = 0; k < 3; ++k) tmp.bytes[k] = std::max<size_t>(need.bytes[k], 16);
+    tmp.ptr[0] = base + w.ccp;
+    tmp.ptr[1] = base + w.irow;
+    tmp.ptr[2] = base + w.val;
+    // the limit guards the extra arrays of a transformation; here they are
+    // temporary and the result takes the CRS arrays' place
+    const size_t limit = p->limit;
+    p->limit = SIZE_MAX;
+    st = csr_to_ccs(p, &tmp, base + w.ccs_work, w.ccs_work_bytes, stream);
+    p->limit = limit;
+    if (st != SPMV_OK) return st;
+    // the copy-back of Phase I: column pointers over IRP, rows over ICOL,
+    // values over VAL (the same sizes: n + 1, nnz, nnz)
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(p, hipMemcpyAsync(irp, tmp.ptr[0], need.bytes[0], hipMemcpyDeviceToDevice, s));
+    if (p->nnz > 0) {
+        HIP_TRY(p, hipMemcpyAsync(icol, tmp.ptr[1], need.bytes[1], hipMemcpyDeviceToDevice, s));
+        HIP_TRY(p, hipMemcpyAsync(val, tmp.ptr[2], need.bytes[2], hipMemcpyDeviceToDevice, s));
+    }
+    p->ccp = irp; p->irow_t = icol; p->val_t = val;
+    p->crs_consumed = true;
+    p->has_coo_row = false; p->irow = nullptr;   // COO-Row used the CRS ICOL and VAL
     return SPMV_OK;
 }
 
@@ -373,6 +547,7 @@ SPMV_API spmv_status csr_to_ell(spmv_plan* p, int column_wise, const spmv_buffer
     (void)work; (void)work_bytes;
     if (!p) return SPMV_E_ARG;
     if (column_wise && !p->has_ccs) return SPMV_E_NOT_READY;
+    if (!column_wise && p->crs_consumed) return SPMV_E_NOT_READY;
     spmv_sizes need;
     spmv_status st = spmv_buffer_sizes(p, column_wise ? SPMV_ELL_COL : SPMV_ELL_ROW, &need);
     if (st != SPMV_OK) return st;
@@ -402,6 +577,7 @@ spmv_status spmvat::plan_exec(const spmv_plan* p, spmv_format f, int variant, co
     switch (f) {
         case SPMV_CRS: {
             if (variant < 0 || variant > 8) return SPMV_E_ARG;
+            if (p->crs_consumed) return SPMV_E_NOT_READY;
             const bool stream = variant == 8 || variant == 1;
             if (variant == 0) HIP_TRY(p, launch_spmv_crs_scalar(dt, p->n, p->irp, p->icol, p->val, x, y, alpha, s));
             else if (stream) HIP_TRY(p, launch_spmv_crs_stream(dt, p->n, p->nnz, p->irp, p->icol, p->val, x, y, alpha, s));
@@ -413,7 +589,7 @@ spmv_status spmvat::plan_exec(const spmv_plan* p, spmv_format f, int variant, co
         }
         case SPMV_COO_ROW:
             if (variant != 0) return SPMV_E_ARG;
-            if (!p->has_coo_row) return SPMV_E_NOT_READY;
+            if (!p->has_coo_row || p->crs_consumed) return SPMV_E_NOT_READY;
             if (p->st.min_row == 0 || p->nnz == 0) HIP_TRY(p, launch_fill_zero(y, ybytes, s));
             HIP_TRY(p, launch_spmv_coo_row(dt, p->n, p->nnz, p->irow, p->icol, p->val, x, y, plan_carries(p), s));
             return SPMV_OK;
@@ -561,7 +737,8 @@ SPMV_API spmv_status at_choose_format_stats(const spmv_stats* st, spmv_dtype dt,
             const double cost = tr + k * ts;
             if (cost < best) { best = cost; cf = f; bt = ts; btr = tr; }
         }
-        if (cf != SPMV_CRS && AT_K_MARGIN * best < k * tcrs) { bf = cf; bv = 0; }
+        const double margin = t->k_margin > 0 ? t->k_margin : AT_K_MARGIN;
+        if (cf != SPMV_CRS && margin * best < k * tcrs) { bf = cf; bv = 0; }
         else { bt = tcrs; btr = 0; }
         *fmt = bf; *variant = bv;
         d.t_crs_hat = tcrs; d.t_fmt_hat = bt; d.t_trans_hat = btr;

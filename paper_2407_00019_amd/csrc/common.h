@@ -87,6 +87,24 @@ __device__ __forceinline__ int last_le(const int* a, int lo, int hi, int q) {
     return lo;
 }
 
+// Lanes of the wave whose `bits` low bits of key equal this lane's, among
+// the lanes in `active`.  Every lane of the wave must call it.
+__device__ __forceinline__ uint64_t match_low_bits(uint32_t key, int bits, uint64_t active) {
+    uint64_t m = active;
+    for (int i = 0; i < bits; ++i) {
+        const uint32_t bit = (key >> i) & 1u;
+        const uint64_t b = __ballot(bit);
+        m &= bit ? b : ~b;
+    }
+    return m;
+}
+
+// Mask of the lanes below this one in its wave.
+__device__ __forceinline__ uint64_t lanes_below() {
+    const int lane = threadIdx.x & (kWave - 1);
+    return lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

@@ -48,23 +48,6 @@ constexpr int kPlaceWaves = 8;
 constexpr int kPlaceThreads = kPlaceWaves * kWave;
 constexpr int kPlaceGrid = 512;
 
-// Lanes of the wave whose `bits` low bits of key equal this lane's, among
-// the lanes in `active`.  Every lane of the wave must call it.
-__device__ __forceinline__ uint64_t match_low_bits(uint32_t key, int bits, uint64_t active) {
-    uint64_t m = active;
-    for (int i = 0; i < bits; ++i) {
-        const uint32_t bit = (key >> i) & 1u;
-        const uint64_t b = __ballot(bit);
-        m &= bit ? b : ~b;
-    }
-    return m;
-}
-
-__device__ __forceinline__ uint64_t lanes_below() {
-    const int lane = threadIdx.x & (kWave - 1);
-    return lane == 0 ? 0ull : (~0ull >> (kWave - lane));
-}
-
 __device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
 
 template <int kBytes> struct Raw;

@@ -27,6 +27,7 @@
 #include "../../include/spmvat.h"
 #include "common.h"
 #include "kernels.h"
+#include "spmv_rows.h"
 
 namespace spmvat {
 
@@ -64,84 +65,14 @@ k_spmv_crs_vector(int n, const int* __restrict__ irp, const int* __restrict__ ic
     if (lane == 0 && row < n) y[row] = s * alpha;
 }
 
-constexpr int kStreamCap = 2048;   // products staged in LDS per chunk
-constexpr int kStreamLong = 256;   // rows longer than this are summed by the whole workgroup
-
-// G lanes per row, 256/G rows per workgroup.  The lanes of a row take its
-// staged products in a stride of G (storage order when G = 1, four LDS reads
-// in flight ahead of the adds) and meet in a butterfly at the end.
 template <typename V, typename X, int G>
 __global__ void __launch_bounds__(kBlock)
 k_spmv_crs_stream(int n, const int* __restrict__ irp, const int* __restrict__ icol, const V* __restrict__ val,
                   const X* __restrict__ x, X* __restrict__ y, X alpha) {
     constexpr int kRows = kBlock / G;
-    __shared__ X prod[kStreamCap];
-    __shared__ int sp[kRows + 1];
-    __shared__ unsigned long long s_long[kBlock / kWave];
-    __shared__ X s_red[kBlock / kWave];
+    __shared__ StreamSmem<X> sm;
     const int r0 = (int)xcd_block(blockIdx.x, gridDim.x) * kRows;
-    const int rows = min(kRows, n - r0);
-    const int t = threadIdx.x;
-    for (int c = t; c <= rows; c += kBlock) sp[c] = irp[r0 + c];
-    __syncthreads();
-    const int end = sp[rows];
-    const int row = t / G, lane = t % G;
-    const int a = row < rows ? sp[row] : end, b = row < rows ? sp[row + 1] : end;
-    const bool lng = (b - a) > kStreamLong;
-    // long rows as a bit mask indexed by row (thread t tests row t)
-    const bool lt = t < rows && (sp[t + 1] - sp[t]) > kStreamLong;
-    const unsigned long long m = __ballot(lt);
-    if ((t & (kWave - 1)) == 0) s_long[t / kWave] = m;
-    __syncthreads();
-    bool any_long = false;
-#pragma unroll
-    for (int w = 0; w < kBlock / kWave; ++w) any_long |= s_long[w] != 0;
-    X s = 0;
-    for (int c0 = sp[0]; c0 < end; c0 += kStreamCap) {
-        const int cl = min(kStreamCap, end - c0);
-#pragma unroll 4
-        for (int q = t; q < cl; q += kBlock)
-            prod[q] = (X)widen(ld_nt(&val[c0 + q])) * x[ld_nt(&icol[c0 + q])];
-        __syncthreads();
-        if (!lng) {
-            const int lo = max(a, c0) - c0, hi = min(b, c0 + cl) - c0;
-            int p = lo + lane;
-            for (; p + 3 * G < hi; p += 4 * G) {
-                const X q0 = prod[p], q1 = prod[p + G], q2 = prod[p + 2 * G], q3 = prod[p + 3 * G];
-                s += q0; s += q1; s += q2; s += q3;
-            }
-            for (; p < hi; p += G) s += prod[p];
-        }
-        if (any_long) {
-            // each long row in turn: the workgroup sums its part of the chunk
-            for (int w = 0; w < kBlock / kWave; ++w) {
-                unsigned long long bits = s_long[w];
-                while (bits) {
-                    const int r = w * kWave + __ffsll((long long)bits) - 1;
-                    bits &= bits - 1;
-                    const int lo = max(sp[r], c0) - c0, hi = min(sp[r + 1], c0 + cl) - c0;
-                    if (lo >= hi) continue;
-                    X part = 0;
-                    for (int q = lo + t; q < hi; q += kBlock) part += prod[q];
-#pragma unroll
-                    for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off, kWave);
-                    if ((t & (kWave - 1)) == 0) s_red[t / kWave] = part;
-                    __syncthreads();
-                    if (t == r * G) {
-                        X tot = 0;
-#pragma unroll
-                        for (int k2 = 0; k2 < kBlock / kWave; ++k2) tot += s_red[k2];
-                        s += tot;
-                    }
-                    __syncthreads();
-                }
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
-    if (lane == 0 && row < rows) y[r0 + row] = s * alpha;
+    crs_stream_rows<V, X, G>(r0, min(kRows, n - r0), irp, icol, val, x, y, alpha, sm);
 }
 
 // ------------------------------------------------------------- ELL
@@ -155,12 +86,7 @@ k_spmv_ell_row(int n, int width, const V* __restrict__ ev, const int* __restrict
                X* __restrict__ y, X alpha) {
     const int i = (int)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= n) return;
-    X s = 0;
-    size_t off = (size_t)i;
-#pragma unroll 8
-    for (int k = 0; k < width; ++k, off += (size_t)n)
-        s += (X)widen(ld_nt(&ev[off])) * x[ld_nt(&ec[off])];
-    y[i] = s * alpha;
+    ell_row_one<V, X>(i, n, width, ev, ec, x, y, alpha);
 }
 
 // Two consecutive rows per thread: one 2-element load per slot for values

@@ -211,7 +211,7 @@ k_scan_reduce(int n, const int* __restrict__ cnt, int* __restrict__ bsum, int* _
             const int c = cnt[j];
             s += c;
             mx = max(mx, c);
-            if (c > kSortSmall) {
+            if (c > kSortSmall && mid_list) {   // lists only for the per-column sort
                 if (c <= kSortMid) mid_list[atomicAdd(&sum->n_mid, 1)] = j;
                 else long_list[atomicAdd(&sum->n_long, 1)] = j;
             }
@@ -284,6 +284,23 @@ k_scan_apply(int n, const int* cnt, const int* __restrict__ bsum, int* __restric
 }
 
 size_t col_scan_bsum_count(int n) { return (size_t)((n + kScanTile - 1) / kScanTile); }
+
+// (start, end) of each listed column, for one copy to the host.
+__global__ void __launch_bounds__(kBlock)
+k_col_extents(int count, const int* __restrict__ list, const int* __restrict__ ccp, int* __restrict__ ext) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= count) return;
+    const int j = list[i];
+    ext[2 * i] = ccp[j];
+    ext[2 * i + 1] = ccp[j + 1];
+}
+
+hipError_t launch_col_extents(int count, const int* list, const int* ccp, int* ext, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_col_extents, dim3((unsigned)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, count,
+                       list, ccp, ext);
+    return hipGetLastError();
+}
 
 hipError_t launch_col_scan(int n, const int* cnt, int* ccp, int* cursor, int* bsum, int* mid_list,
                            int* long_list, ColSummary* sum, hipStream_t s) {

@@ -45,9 +45,12 @@ hipError_t launch_expand_ptr(int n, const int* ptr, int* out, hipStream_t s);
 // Column counts (added into cnt); bw = the matrix bandwidth from the row
 // statistics selects the LDS-privatised kernel when its window fits.
 hipError_t launch_col_count(int n, int bw, const int* irp, const int* icol, int* cnt, hipStream_t s);
+// mid_list = long_list = nullptr: no lists of long columns (n_mid, n_long stay 0)
 hipError_t launch_col_scan(int n, const int* cnt, int* ccp, int* cursor, int* bsum,
                            int* mid_list, int* long_list, ColSummary* sum, hipStream_t s);
 size_t col_scan_bsum_count(int n);   // per array; the scan needs two (sums, maxima)
+// ext[2i], ext[2i+1] = ccp[list[i]], ccp[list[i] + 1]
+hipError_t launch_col_extents(int count, const int* list, const int* ccp, int* ext, hipStream_t s);
 hipError_t launch_ccs_scatter(int n, int bw, const int* irp, const int* icol, int* cursor,
                               unsigned long long* keys, hipStream_t s);
 hipError_t launch_ccs_sort_small(int n, const int* ccp, unsigned long long* keys, const void* val,
@@ -78,6 +81,33 @@ CcsGeom ccs_geom(int n);
 hipError_t launch_ccs_bucketed(const CcsGeom& g, int n, int64_t nnz, const int* irp, const int* icol,
                                const void* val, int vbytes, int* table, int* csum, uint32_t* bkey, void* bval,
                                int* ccp, int* irow_t, void* val_t, ColSummary* sum, hipStream_t s);
+// Banded CRS -> CCS for matrices of limited bandwidth (a two-level stable
+// counting sort with coalesced stores): per-(tile, wave) counts over the
+// 128-column blocks of each row tile's column window, a per-block walk over
+// the tiles giving every stretch its start, the ordered distribution to the
+// blocks, then a stable per-block placement by column staged in LDS.
+struct WccsGeom {
+    int rows, tiles;       // rows per tile, tiles
+    int nb;                // 128-column blocks
+    int nwbmax;            // window blocks of the widest window
+    int wb_bits;           // bits of a window block index
+    int64_t table;         // table counts: tiles x waves x nwbmax
+    bool usable;           // the window fits the kernels' LDS and n fits the packed key
+};
+constexpr uint32_t kWccsOutside = 1;    // an entry outside its tile's window (CRS changed since the plan)
+struct WccsInfo {
+    uint32_t flags;
+    int32_t kmax;          // the longest column
+};
+WccsGeom wccs_geom(int n, int bw, int max_row);
+// counts and the per-block walk; bcnt[b] receives the length of block b
+hipError_t launch_wccs_front(const WccsGeom& g, int n, int bw, const int* irp, const int* icol, int* table,
+                             int* bcnt, WccsInfo* info, hipStream_t s);
+// distribution (key[nnz], sval[nnz] staging) and placement; bstart[nb + 1]
+// holds the scanned block lengths
+hipError_t launch_wccs_back(const WccsGeom& g, int n, int bw, int vbytes, const int* irp, const int* icol,
+                            const void* val, const int* table, const int* bstart, uint32_t* key, void* sval,
+                            int* ccp, int* irow_t, void* val_t, WccsInfo* info, hipStream_t s);
 hipError_t launch_ell_pack(int n, int width, const int* ptr, const int* idx, const void* val,
                            int vbytes, void* ell_val, int* ell_idx, hipStream_t s);
 
@@ -109,6 +139,24 @@ size_t coo_carry_bytes(int64_t nnz);
 int64_t coo_row_static_max_nnz();
 hipError_t launch_spmv_coo_row_static(int dtype, int n, int64_t nnz, const int* irow, const int* icol,
                                       const void* val, const void* x, void* y, hipStream_t s);
+
+// ---- serving: one batched chain step over every running job (binary32)
+constexpr int kServeCrs = 0, kServeEll = 1;
+constexpr int kServeCoarseBits = 6;   // the coarse map holds the job of every 64th work item
+constexpr int kServeThreads = 256;    // threads of the step kernel: an ELL-Row item is 256 rows
+struct ServeStep {
+    const int* a0;            // CRS: row pointers; ELL-Row: slot-major column indices
+    const int* a1;            // CRS: column indices
+    const float* val;         // CRS values or ELL-Row slot-major values
+    const float* x;           // input of this step
+    float* y;                 // output of this step
+    int32_t n, kind, param;   // param: lanes per row (CRS) or the ELL width
+    int32_t item0;            // first work item of the job in this step
+    int32_t rows_per_item;
+    float alpha;              // y = alpha A x
+};
+int serve_crs_lanes(int n, int64_t nnz);
+hipError_t launch_serve_step(const ServeStep* jobs, int njobs, const int* coarse, int items, hipStream_t s);
 
 // ---- value conversion (to: 1 F32, 2 BF16, 3 F16)
 hipError_t launch_convert(int to, int64_t m, const double* in, void* out, hipStream_t s);

@@ -20,6 +20,8 @@ struct spmv_plan {
     size_t work_bytes = 0;
     spmv_stats st{};
     size_t limit = 0;
+    int ccs_alg = 0;                  // spmv_ccs_algorithm; 0 lets the structure decide
+    bool crs_consumed = false;        // csr_to_ccs_inplace overwrote the CRS arrays with CCS
     // formats built so far (borrowed caller buffers; arrays may be null when nnz = 0)
     bool has_coo_row = false, has_ccs = false, has_coo_col = false;
     const int32_t* irow = nullptr;                                            // COO-Row

@@ -89,12 +89,16 @@ def build_jobs(specs, seed_x: int = 7) -> list:
     return jobs
 
 
-def load_table() -> spmvat.at_table:
+def load_table(warn=True) -> spmvat.at_table:
     path = os.path.join(_HERE, "at_table.json")
     if not os.path.exists(path):
         return spmvat.at_table_build([], [], None, 1.0)
     with open(path) as f:
-        return spmvat.at_table_from_json(json.load(f))
+        d = json.load(f)
+    if warn and spmvat.table_matches_kernels(d) is False:
+        print("[serve] warning: at_table.json was measured with other kernel sources "
+              "(re-run python -m paper_2407_00019_amd.offline)", file=sys.stderr, flush=True)
+    return spmvat.at_table_from_json(d)
 
 
 def run(jobs, policy: int, slots: int = DEFAULT_SLOTS, hbm_cap: int = 200 << 30, table=None, arrivals=None,
@@ -143,31 +147,35 @@ def _median_run(runs, key):
     return order[len(order) // 2]
 
 
-def compare(jobs_host, slots, hbm_cap, rate, log=print, repeats: int = 3) -> dict:
+def compare(jobs_host, slots, hbm_cap, rate, log=print, repeats: int = 3, modes=("burst", "poisson"),
+            policies=(("crs", 1), ("auto", 0)), table=None) -> dict:
     """Both policies on one trace, each replayed `repeats` times, alternating
     policies so that drifts of the machine hit both alike: burst first (all
     jobs at t = 0) to find the always-CRS capacity, then Poisson arrivals at
     `rate` jobs/s (rate 'auto': 70% of that capacity).  Each policy reports
     its median run (by jobs/s for the burst, by p50 for Poisson) and every
     run's figure."""
-    table = load_table()
+    table = load_table() if table is None else table
     out = {"slots": slots, "hbm_cap_bytes": hbm_cap, "repeats": repeats}
     zeros = [0.0] * len(jobs_host)
-    runs = {"crs": [], "auto": []}
+    runs = {name: [] for name, _ in policies}
     for rep in range(repeats):
-        for name, pol in (("crs", 1), ("auto", 0)):
+        for name, pol in policies:
             res, wall = run(jobs_host, pol, slots, hbm_cap, table, zeros)
             runs[name].append(summarize(res))
             log(f"[serve] burst {name} #{rep}: {runs[name][-1]}")
     out["burst"] = {name: dict(_median_run(r, "jobs_per_s"), runs_jobs_per_s=[x["jobs_per_s"] for x in r])
                     for name, r in runs.items()}
-    lam = 0.7 * out["burst"]["crs"]["jobs_per_s"] if rate == "auto" else float(rate)
+    if "poisson" not in modes:
+        return out
+    cap = out["burst"]["crs"]["jobs_per_s"] if "crs" in out["burst"] else list(out["burst"].values())[0]["jobs_per_s"]
+    lam = 0.7 * cap if rate == "auto" else float(rate)
     u = np.random.default_rng(20240700019).random(len(jobs_host))
     arr = np.cumsum(-np.log1p(-u) / lam)
     arr -= arr[0]
-    runs = {"crs": [], "auto": []}
+    runs = {name: [] for name, _ in policies}
     for rep in range(repeats):
-        for name, pol in (("crs", 1), ("auto", 0)):
+        for name, pol in policies:
             res, wall = run(jobs_host, pol, slots, hbm_cap, table, arr.tolist())
             runs[name].append(summarize(res))
             log(f"[serve] poisson {name} #{rep}: {runs[name][-1]}")
@@ -187,14 +195,26 @@ def main(argv=None):
     ap.add_argument("--rate", default="auto")
     ap.add_argument("--n-max", type=float, default=5e5)
     ap.add_argument("--repeats", type=int, default=3)
+    ap.add_argument("--modes", default="burst,poisson", help="burst, poisson or both")
+    ap.add_argument("--policies", default="crs,auto", help="crs (always CRS), auto, auto-release (policy 2)")
+    ap.add_argument("--kind", default="all", help="all, banded or random: the jobs of one structure only")
+    ap.add_argument("--convert-all", action="store_true",
+                    help="a table without measured points (D* = +inf): the auto policies convert every job "
+                         "whose ELL-Row fits")
     a = ap.parse_args(argv)
+    pol_codes = {"crs": 1, "auto": 0, "auto-release": 2}
+    policies = tuple((p, pol_codes[p]) for p in a.policies.split(","))
     t0 = time.time()
     specs = gen.serving_jobs(a.jobs, rate_per_s=0.0, n_max=a.n_max)
+    if a.kind != "all":
+        specs = [sp for sp in specs if sp.kind == a.kind]
     jobs = build_jobs(specs)
     print(f"[serve] built {len(jobs)} jobs ({sum(j.nnz for j in jobs) / 1e6:.1f}M nonzeros) in "
           f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     out = compare(jobs, a.slots, int(a.cap_gb * (1 << 30)), a.rate,
-                  log=lambda s: print(s, file=sys.stderr, flush=True), repeats=a.repeats)
+                  log=lambda s: print(s, file=sys.stderr, flush=True), repeats=a.repeats,
+                  modes=tuple(a.modes.split(",")), policies=policies,
+                  table=spmvat.at_table_build([], [], None, 1.0) if a.convert_all else None)
     print(json.dumps(out), flush=True)
 
 

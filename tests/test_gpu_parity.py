@@ -600,6 +600,91 @@ def test_ccs_duplicate_column_longer_than_n(n, reps):
         assert oracle.rel_l2(y, yref) <= TOL64, (key, oracle.rel_l2(y, yref))
 
 
+def wide_random_rows(n, per_row, seed):
+    """Sorted random rows of `per_row` columns each over all n columns: a
+    512-row tile then touches more columns than the windowed placement keeps
+    in LDS."""
+    rng = np.random.default_rng(seed)
+    icol = np.empty(n * per_row, np.int32)
+    for i in range(n):
+        icol[i * per_row:(i + 1) * per_row] = np.sort(rng.choice(n, per_row, replace=False))
+    irp = np.arange(0, n * per_row + 1, per_row, dtype=np.int32)
+    return gen.Crs(n, irp, icol, rng.standard_normal(icol.shape[0]), f"wide_random_{n}x{per_row}")
+
+
+CCS_CASES = {
+    "stencil27_e12": lambda: gen.stencil27(12, 12, 12, 3),
+    "band_edges_3000": lambda: band_edges(20000, 3000, 76),
+    "dup_long": lambda: dup_long_column(600, 128, 77),
+    "wide_random": lambda: wide_random_rows(60000, 150, 78),
+    "rand_unsorted": lambda: gen.random_small(2500, 2, 9, False, False, 0.2, integer_values=False),
+}
+
+
+@pytest.mark.parametrize("alg", ["sort", "bucketed", "banded"])
+@pytest.mark.parametrize("case", sorted(CCS_CASES))
+def test_ccs_every_algorithm(case, alg):
+    """Each CRS -> CCS algorithm, selected on the plan, on matrices of every
+    kind: a stencil, a band at its edges, a column of 76,800 duplicate
+    entries (longer than n: the sort ranks it across sorted chunks), random
+    rows over 60,000 columns, unsorted rows.  CCS and COO-Column bit-exact
+    with the oracle, the longest column right, COO-Column SpMV within 1e-13."""
+    import torch
+    spmvat = lib_ready()
+    m = CCS_CASES[case]()
+    assert oracle.validate_crs(m.n, m.irp, m.icol) == 0
+    irp, icol, val = to_dev(m)
+    plan = spmvat.Plan(irp, icol, val)
+    code = {"sort": spmvat.CCS_SORT, "bucketed": spmvat.CCS_BUCKETED, "banded": spmvat.CCS_BANDED}[alg]
+    ccp, irow_t, val_t = plan.to_ccs(algorithm=code)
+    (jcol,) = plan.to_coo(column_wise=True)
+    o_ccp, o_irow_t, o_val_t = oracle.csr_to_ccs(m.n, m.irp, m.icol, m.val)
+    assert np.array_equal(host(ccp), o_ccp)
+    assert np.array_equal(host(irow_t), o_irow_t)
+    assert np.array_equal(bits(host(val_t)), bits(o_val_t))
+    assert np.array_equal(host(jcol), oracle.ccs_to_coo_col(m.n, o_ccp))
+    assert plan.stats.max_col == int(np.diff(o_ccp).max())
+    x = gen.x_uniform(m.n, 13)
+    yref = oracle.spmv_crs(m.n, m.irp, m.icol, m.val, x)
+    y = host(plan.spmv(spmvat.COO_COL, torch.from_numpy(x).to("cuda:0")))
+    assert oracle.rel_l2(y, yref) <= TOL64
+    plan.close()
+
+
+@pytest.mark.parametrize("case", ["stencil27_e12", "dup_long", "rand_unsorted"])
+def test_ccs_in_place_copy_back(case):
+    """The in-place CCS (Phase I with its copy-back): the plan's own CRS
+    tensors end up holding the oracle's column pointers, row numbers and
+    values bit for bit; COO-Column and ELL-Column built from them match the
+    oracle, COO-Column SpMV is within 1e-13, and CRS SpMV is refused."""
+    import torch
+    spmvat = lib_ready()
+    m = CCS_CASES[case]()
+    irp, icol, val = to_dev(m)
+    plan = spmvat.Plan(irp, icol, val)
+    plan.set_limit(1 << 40)
+    ccp, irow_t, val_t = plan.to_ccs_inplace()
+    assert ccp.data_ptr() == irp.data_ptr() and irow_t.data_ptr() == icol.data_ptr()
+    o_ccp, o_irow_t, o_val_t = oracle.csr_to_ccs(m.n, m.irp, m.icol, m.val)
+    assert np.array_equal(host(irp), o_ccp)
+    assert np.array_equal(host(icol), o_irow_t)
+    assert np.array_equal(bits(host(val)), bits(o_val_t))
+    (jcol,) = plan.to_coo(column_wise=True)
+    assert np.array_equal(host(jcol), oracle.ccs_to_coo_col(m.n, o_ccp))
+    (cv, cr), wc = plan.to_ell(column_wise=True)
+    o_cv, o_cr = oracle.ccs_to_ell_col(m.n, o_ccp, o_irow_t, o_val_t)
+    assert np.array_equal(bits(host(cv)), bits(o_cv)) and np.array_equal(host(cr), o_cr)
+    x = gen.x_uniform(m.n, 14)
+    xd = torch.from_numpy(x).to("cuda:0")
+    yref = oracle.spmv_crs(m.n, m.irp, m.icol, m.val, x)
+    assert oracle.rel_l2(host(plan.spmv(spmvat.COO_COL, xd)), yref) <= TOL64
+    with pytest.raises(spmvat.SpmvError) as e:
+        plan.spmv(spmvat.CRS, xd, variant=8)
+    assert e.value.status == spmvat.SPMV_E_NOT_READY
+    torch.cuda.synchronize()
+    plan.close()
+
+
 def test_binding_refuses_vectors_that_do_not_fit_the_plan():
     """x and y of the wrong element type, too short, on the host, strided or
     overlapping are refused by the binding before any kernel runs, and the
