@@ -222,6 +222,68 @@ def locality(bw):
     return 0 if bw <= spmvat.AT_LOCAL_BAND else 1
 
 
+def model_seconds(cm, fmt, st, k, vb, xb):
+    """The cost model's estimate (seconds) of the transformation into fmt plus
+    k SpMVs in it, or of k CRS SpMVs (fmt = "crs", the faster CRS variant),
+    as the on-line k-aware rule computes it."""
+    loc = locality(st.bandwidth)
+    b = bucket(st.d_mat)
+    n, nnz, w = st.n, st.nnz, st.max_row
+    launch = cm["launch_s"]
+
+    def est(bytes_, rate, launches):
+        return bytes_ / rate + launches * launch if rate > 0 else math.inf
+    if fmt == "crs":
+        rates = cm["spmv_bps"][loc][str(spmvat.CRS)]
+        return k * min(est(_bytes("crs", n, nnz, w, vb, xb), rates[v][b], 1) for v in (0, 1))
+    rate = cm["spmv_bps"][loc][str(spmvat.ELL_ROW)][0][b]
+    trate = cm["trans_bps"][loc][str(spmvat.ELL_ROW)][b]
+    return est(_trans_bytes("ell_row", n, nnz, w, vb), trate, 1) + k * est(_bytes("ell_row", n, nnz, w, vb, xb), rate, 1)
+
+
+def calibrate_margin(cm, jobs=96, reps=5, quantile=75.0):
+    """The k-aware rule's margin from the model's error on the serving
+    stream: for each of the first `jobs` jobs where ELL-Row fits, the ratio
+    (transformation + k ELL-Row SpMVs) / (k CRS SpMVs) is predicted by the
+    cost model and measured (binary32 values, as the server stores them);
+    the margin is exp of the given percentile of |ln(predicted / measured)|,
+    so that a conversion is acted on only when its predicted gain exceeds
+    the model's usual error."""
+    import gen
+    dev = torch.device("cuda:0")
+    errs = []
+    for spec in gen.serving_jobs(jobs, rate_per_s=0.0):
+        m = spec.matrix()
+        irp = torch.from_numpy(m.irp).to(dev)
+        icol = torch.from_numpy(m.icol).to(dev)
+        val = torch.from_numpy(m.val).to(dev).float()
+        x = torch.from_numpy(gen.x_uniform(m.n, 3)).to(dev).float()
+        y = torch.empty_like(x)
+        plan = spmvat.Plan(irp, icol, val)
+        st = plan.stats
+        s, _ = plan.sizes(spmvat.ELL_ROW)
+        if s != spmvat.SPMV_OK:
+            plan.close()
+            continue
+        t_crs = time_call(lambda: plan.spmv(spmvat.CRS, x, y, 1), reps) * 1e-3
+        ell = plan._alloc(spmvat.ELL_ROW)[0]
+        t_tr = time_call(lambda: spmvat.csr_to_ell(plan.handle, 0, ell), reps) * 1e-3
+        t_ell = time_call(lambda: plan.spmv(spmvat.ELL_ROW, x, y, 0), reps) * 1e-3
+        k = spec.k
+        meas = (t_tr + k * t_ell) / (k * t_crs)
+        pred = model_seconds(cm, "ell_row", st, k, 4, 4) / model_seconds(cm, "crs", st, k, 4, 4)
+        if math.isfinite(pred) and pred > 0:
+            errs.append(abs(math.log(pred / meas)))
+        plan.close()
+        del ell
+    torch.cuda.empty_cache()
+    if not errs:
+        return None
+    q = float(np.percentile(errs, quantile))
+    return {"k_margin": math.exp(q), "jobs": len(errs), "quantile": quantile,
+            "median_abs_ln_err": float(np.median(errs)), "max_abs_ln_err": float(max(errs))}
+
+
 def main(argv=None):
     import gen
     ap = argparse.ArgumentParser()
@@ -233,6 +295,8 @@ def main(argv=None):
     ap.add_argument("--families", default="scattered,local")
     ap.add_argument("--refit", default=None, help="recompute the D-R models of an existing table and exit")
     ap.add_argument("--table1", action="store_true", help="the off-line phase on the Table 1 stand-ins")
+    ap.add_argument("--margin-jobs", type=int, default=96,
+                    help="serving-stream jobs that calibrate the k-aware margin (0: keep the default)")
     a = ap.parse_args(argv)
     if a.table1:
         out = a.out if a.out != os.path.join(_HERE, "at_table.json") else os.path.join(_HERE, "table1_standins.json")
@@ -275,7 +339,8 @@ def main(argv=None):
     # per family and over all benchmark points together
     f64 = [p["f64"] for p in points if "f64" in p]
     fams = [p["family"] for p in points if "f64" in p]
-    table = {"c": a.c, "machine": torch.cuda.get_device_name(0), "points": len(f64)}
+    table = {"c": a.c, "machine": torch.cuda.get_device_name(0), "points": len(f64),
+             "kernel_source_sha": spmvat.kernel_source_sha()}
     for base in ("scalar", "best"):
         for fam in sorted(set(fams)) + ["all"]:
             sel = [q for q, f in zip(f64, fams) if fam == "all" or f == fam]
@@ -346,10 +411,15 @@ def main(argv=None):
     table["cost_model"] = {"spmv_bps": spmv_bps, "trans_bps": trans_bps, "launch_s": launch_s,
                            "local_band": spmvat.AT_LOCAL_BAND, "d_edges": list(spmvat.AT_DBUCKET_EDGES)}
     add_rd_models(table)
+    if a.margin_jobs > 0:
+        cal = calibrate_margin(table["cost_model"], a.margin_jobs, max(3, a.reps - 2))
+        if cal:
+            table["k_margin"] = cal["k_margin"]
+            table["k_margin_calibration"] = cal
     table["sweep"] = points
     with open(a.out, "w") as f:
         json.dump(table, f, indent=1, default=float)
-    print(json.dumps({k: v for k, v in table.items() if k.startswith("d_star")} |
+    print(json.dumps({k: v for k, v in table.items() if k.startswith(("d_star", "k_margin"))} |
                      {"launch_us": launch_s * 1e6, "out": a.out}), flush=True)
 
 

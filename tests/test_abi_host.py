@@ -180,6 +180,41 @@ def test_k_aware_needs_a_gain_beyond_the_margin():
         assert oracle.choose_k_aware(1000, crs_b / 1e12, cands, spmvat.AT_K_MARGIN) == want_o
 
 
+def test_table_margin_replaces_the_default():
+    """A table that carries its own margin (measured by the off-line phase)
+    decides with it: a 15% predicted gain converts under the default 1.1
+    and keeps CRS under a measured 1.2, as the oracle's rule says."""
+    spmvat = _lib()
+    n, nnz, w = 100000, 2_600_000, 26
+    st = _stats(n, nnz, w, 0.0)
+    crs_b = 12 * nnz + 4 * (n + 1) + 16 * n
+    ell_b = 12 * n * w + 16 * n
+    ell_rate = 1e12 * 1.15 * ell_b / crs_b
+    cands = {"ell_row": (0.0, crs_b / 1e12 / 1.15)}
+    for margin, want in ((0.0, spmvat.ELL_ROW), (1.2, spmvat.CRS), (1.1, spmvat.ELL_ROW)):
+        t = _calibrated(spmvat, 1e12, 1e12, 1e9, ell_rate, 1e9, 1e30)
+        t.k_margin = margin
+        f, v, why = spmvat.at_choose_format_stats(st, 0, 1 << 40, t, 1000)
+        assert f == want, (margin, f)
+        used = margin if margin > 0 else spmvat.AT_K_MARGIN
+        want_o = oracle.choose_k_aware(1000, crs_b / 1e12, cands, used)
+        assert want_o == ("crs" if want == spmvat.CRS else "ell_row")
+
+
+def test_off_line_table_is_stamped_with_the_kernel_sources():
+    """The committed auto-tuning table names the kernel sources it was
+    measured with (a hash of csrc/*.hip and *.h), carries a measured
+    margin, and the library's JSON reader takes the margin over."""
+    import json
+    spmvat = _lib()
+    with open(os.path.join(ROOT, "paper_2407_00019_amd", "at_table.json")) as f:
+        d = json.load(f)
+    assert isinstance(d.get("kernel_source_sha"), str) and len(d["kernel_source_sha"]) == 16
+    assert spmvat.table_matches_kernels(d) in (True, False)
+    assert d["k_margin"] >= 1.0
+    assert spmvat.at_table_from_json(d).k_margin == pytest.approx(d["k_margin"])
+
+
 def test_cost_model_cell_follows_locality_and_d_bucket():
     """The k-aware choice reads the table cell of the matrix's locality class
     (bandwidth <= 65536 or not) and D_mat bucket (edges 1/16, 1/8, 1/4, 1/2,
