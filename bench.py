@@ -211,6 +211,39 @@ class PathRunner:
             T(f"{L}spmv_ell_col", sp.spmv_exec, plan, sp.ELL_COL, 0, self.x, self.y, reps=R)
         sp.spmv_plan_destroy(plan)
 
+    def ccs_algorithms(self, reps=5):
+        """Median time (ms) of CRS -> CCS with each algorithm the matrix
+        admits, on torch's current stream (the plan built outside the events)."""
+        import torch
+        sp = self.sp
+        out = {}
+        for name, alg in (("sort", sp.CCS_SORT), ("bucketed", sp.CCS_BUCKETED), ("banded", sp.CCS_BANDED)):
+            plan = sp.spmv_plan_create(self.n, self.nnz, self.irp, self.icol, self.val, self.dtype, self.work)
+            try:
+                sp.spmv_plan_set_ccs_algorithm(plan, alg)
+            except sp.SpmvError:
+                sp.spmv_plan_destroy(plan)
+                continue
+            sp.spmv_plan_set_limit(plan, 1 << 45)
+            buf, work, _, _ = alloc_like(sp, plan, sp.CCS, self.vt, self.dev)
+            ts = []
+            for _ in range(reps + 1):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                sp.csr_to_ccs(plan, buf, work)
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            out[name] = round(statistics.median(ts[1:]) * 1e3, 1)
+            sp.spmv_plan_destroy(plan)
+            del buf, work
+        return out
+
+    def release(self):
+        """Drops the device buffers (the next workload needs the memory)."""
+        self.buf = {}
+        self.work = self.y = None
+
     def outputs(self, fmt, variant=0):
         """y of one format (after the steps), for the error report."""
         sp = self.sp
@@ -226,56 +259,19 @@ class PathRunner:
         return y
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="stencil27_128", choices=["stencil27_128", "laplace64", "powerlaw"])
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--no-precision", action="store_true", help="skip the reduced-precision rows")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-oracle SpMV sample")
-    ap.add_argument("--spmv-reps", type=int, default=3,
-                    help="back-to-back SpMVs per format in each step (one event pair around them)")
-    ap.add_argument("--serve-jobs", type=int, default=256,
-                    help="jobs of the serving stream replayed after the timed steps (0: skip)")
-    ap.add_argument("--copy-calib", action="store_true",
-                    help="run one 1 GiB device copy first (reference kernel for the HBM byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding this path "
-              "over several GPUs is designed but not built", file=sys.stderr)
-        sys.exit(2)
-
+def measure(spmvat, m, cfg_index, steps, warmup, spmv_reps, precision, table, log_tag):
+    """Times `steps` passes of the whole path over one matrix (after `warmup`
+    untimed ones) and derives the per-format rates, transformation costs in
+    CRS-SpMV units, SP and R_ell, the format decisions and, for each value
+    type in `precision`, the reduced-precision rows."""
     import torch
     import gen
-    import paper_2407_00019_amd as spmvat
-    if not os.path.exists(spmvat.LIB_PATH):
-        import __graft_entry__
-        __graft_entry__.build()
-
     dev = torch.device("cuda:0")
-    t0 = time.time()
-    builders = {"laplace64": (gen.laplace_64x64, 1), "stencil27_128": (gen.stencil27_128, 2),
-                "powerlaw": (gen.powerlaw, 3)}
-    build_m, cfg_index = builders[args.workload]
-    m = build_m()
-    cfg_seed = gen.seed_for(cfg_index)
-    x64 = gen.x_uniform(m.n, cfg_seed)
-    log(f"[bench] workload {m.name}: n={m.n} nnz={m.nnz} generated in {time.time() - t0:.1f}s")
+    x64 = gen.x_uniform(m.n, gen.seed_for(cfg_index))
     irp = torch.from_numpy(m.irp).to(dev)
     icol = torch.from_numpy(m.icol).to(dev)
     val = torch.from_numpy(m.val).to(dev)
     xd = torch.from_numpy(x64).to(dev)
-    if args.copy_calib:
-        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
-        b = torch.empty_like(a)
-        a.fill_(1.0)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-
     # lane-group width: the smallest power of two covering half the mean row
     # length (on the 27-point stencil 16 lanes take 223 us, 32 lanes 301 us:
     # a group that is mostly idle lanes keeps fewer rows in flight)
@@ -284,41 +280,39 @@ def main():
     while wsub < 64 and wsub < mu / 2:
         wsub *= 2
     v_sub = 1 + int(math.log2(wsub))          # explicit lane-group variant of that width
-    runners = [PathRunner(spmvat, irp, icol, val, xd, "", variants=(0, v_sub, 8), spmv_reps=args.spmv_reps)]
-    if not args.no_precision:
+    runners = [PathRunner(spmvat, irp, icol, val, xd, "", variants=(0, v_sub, 8), spmv_reps=spmv_reps)]
+    tags = {spmvat.F32: "f32", spmvat.BF16: "bf16", spmvat.F16: "f16"}
+    if precision:
         x32 = xd.float()
-        for dt, tag in ((spmvat.F32, "f32"), (spmvat.BF16, "bf16")):
+        for dt in precision:
             v = spmvat.convert_values(val, dt)
-            runners.append(PathRunner(spmvat, irp, icol, v, x32, f"{tag}:", with_column=False, variants=(8,),
-                                      spmv_reps=args.spmv_reps))
-    table, table_path = load_at_table(spmvat)
+            runners.append(PathRunner(spmvat, irp, icol, v, x32, f"{tags[dt]}:", with_column=False, variants=(8,),
+                                      spmv_reps=spmv_reps))
     torch.cuda.synchronize()
-
     T = Timer()
 
     def one_step():
         for r in runners:
             r.step(T, table if r.label == "" else None)
-        if not args.no_precision:
-            T("f32:convert", spmvat.spmv_convert_values, val, runners[1].val, spmvat.F32)
-            T("bf16:convert", spmvat.spmv_convert_values, val, runners[2].val, spmvat.BF16)
+        for r, dt in zip(runners[1:], precision):
+            T(f"{tags[dt]}:convert", spmvat.spmv_convert_values, val, r.val, dt)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         one_step()
     torch.cuda.synchronize()
     T.clear()
-    log(f"[bench] warmup done ({args.warmup} steps); timing {args.steps} steps")
+    log(f"[bench] {log_tag}: warmup done ({warmup} steps); timing {steps} steps")
     torch.cuda.synchronize()
     w0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         one_step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     raw = T.results_ms()
     ms = {k: statistics.mean(v) for k, v in raw.items()}
     med = {k: statistics.median(v) for k, v in raw.items()}
-    ms_per_step = 1000.0 * wall / args.steps
-    log(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step")
+    ms_per_step = 1000.0 * wall / steps
+    log(f"[bench] {log_tag}: timed {steps} steps: {ms_per_step:.3f} ms/step")
 
     n, nnz = m.n, m.nnz
     r0 = runners[0]
@@ -361,12 +355,13 @@ def main():
         r_ell = {"vs_crs_scalar": round(sp_ell["vs_crs_scalar"] / (med["ell_row"] / t_crs0), 4),
                  "vs_crs_best": round(sp_ell["vs_crs_best"] / (med["ell_row"] / t_crs1), 4)}
 
-    precision = {}
-    if not args.no_precision:
+    prec = {}
+    if precision:
         # reference: this run's binary64 SpMV (the GPU parity tests tie it to the
         # CPU oracle within 1e-13)
         y64 = r0.outputs(spmvat.CRS, 8)
-        for r, tag, vb in ((runners[1], "f32", 4), (runners[2], "bf16", 2)):
+        for r, dt in zip(runners[1:], precision):
+            tag, vb = tags[dt], (4 if dt == spmvat.F32 else 2)
             entry = {}
             pairs = [("crs", "spmv_crs8", spmvat.CRS, 8)] + ([("ell_row", "spmv_ell_row", spmvat.ELL_ROW, 0)]
                                                              if r.ell_row else [])
@@ -380,9 +375,78 @@ def main():
                     "gbs": round(gbs(b_, t_ms), 1), "frac": round(gbs(b_, t_ms) / HBM_PEAK_GBS, 4),
                     "speedup_vs_f64": round(med[key] / t_ms, 3), "rel_l2_vs_f64": float(f"{err:.3e}")}
             entry["convert_us"] = round(ms[f"{tag}:convert"] * 1e3, 2)
-            precision[tag] = entry
+            prec[tag] = entry
 
+    if r0.with_column:
+        transforms["ccs"]["algorithms_median_us"] = r0.ccs_algorithms()
+    decision = {"d_star": table.d_star if math.isfinite(table.d_star) else "inf",
+                "choice": spmvat.FORMAT_NAMES[r0.decision[0]] if hasattr(r0, "decision") else None,
+                "choice_k100": spmvat.FORMAT_NAMES[r0.decision_k100[0]] if hasattr(r0, "decision_k100") else None}
+    if hasattr(r0, "decision_k100"):
+        why = r0.decision_k100[2]
+        decision["k100_estimates_us"] = {"crs": round(why.t_crs_hat * 1e6, 2), "format": round(why.t_fmt_hat * 1e6, 2),
+                                         "transform": round(why.t_trans_hat * 1e6, 2)}
+    for r in runners:
+        r.release()
+    del runners
+    return {"m": m, "n": n, "nnz": nnz, "w": w, "wsub": wsub, "d_mat": r0.stats.d_mat, "ms_per_step": ms_per_step,
+            "bandwidth": r0.stats.bandwidth,
+            "per_format": per_format, "best": best, "transforms": transforms, "sp_ell_row": sp_ell,
+            "r_ell_row": r_ell, "precision": prec, "at_decision": decision, "x64": x64, "ell_row": r0.ell_row}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="stencil27_128", choices=["stencil27_128", "laplace64", "powerlaw"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-precision", action="store_true", help="skip the reduced-precision rows")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workloads (5-point Laplacian latencies, power-law rows)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-oracle SpMV sample")
+    ap.add_argument("--spmv-reps", type=int, default=3,
+                    help="back-to-back SpMVs per format in each step (one event pair around them)")
+    ap.add_argument("--serve-jobs", type=int, default=2048,
+                    help="jobs of the serving stream replayed after the timed steps (0: skip)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run one 1 GiB device copy first (reference kernel for the HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding this path "
+              "over several GPUs is designed but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import gen
+    import paper_2407_00019_amd as spmvat
+    if not os.path.exists(spmvat.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+
+    dev = torch.device("cuda:0")
+    if args.copy_calib:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    builders = {"laplace64": (gen.laplace_64x64, 1), "stencil27_128": (gen.stencil27_128, 2),
+                "powerlaw": (gen.powerlaw, 3)}
+    table, table_path = load_at_table(spmvat)
+    t0 = time.time()
+    build_m, cfg_index = builders[args.workload]
+    m = build_m()
+    log(f"[bench] workload {m.name}: n={m.n} nnz={m.nnz} generated in {time.time() - t0:.1f}s")
+    precision = () if args.no_precision else (spmvat.F32, spmvat.BF16, spmvat.F16)
+    h = measure(spmvat, m, cfg_index, args.steps, args.warmup, args.spmv_reps, precision, table, m.name)
+    n, nnz, w, best = h["n"], h["nnz"], h["w"], h["best"]
+    per_format = h["per_format"]
     head = per_format[best]
+    wsub = h["wsub"]
     ell2 = f"k_spmv_ell_row2<double, double, {w if 0 < w <= 32 else 0}>"   # widths 1..32 are unrolled kernels
     kernel_names = {"ell_row": ell2 if n % 2 == 0 else "k_spmv_ell_row<double, double>",
                     f"crs_subwave{wsub}": f"k_spmv_crs_vector<double, double, {wsub}>",
@@ -402,29 +466,82 @@ def main():
     roofline = {"bound": "hbm", "kernel": kernel_names[best], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": head["bytes"], "mean_launch_us": head["us"]}
-
+    decision = dict(h["at_decision"])
+    decision["table"] = os.path.relpath(table_path, ROOT) if table_path else None
+    decision["table_matches_kernels"] = table_matches_kernels(table_path)
+    decision.update(model_decision(table_path, h))
     out = {
         "metric": METRIC, "value": roofline["achieved"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": m.name, "n": n, "nnz": nnz, "d_mat": r0.stats.d_mat, "ell_width": w,
+        "warmup": args.warmup, "ms_per_step": round(h["ms_per_step"], 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": m.name, "n": n, "nnz": nnz, "d_mat": h["d_mat"], "ell_width": w,
                    "best_format": best, "headline": f"best-format binary64 SpMV, {m.name}"},
         "roofline": roofline,
         "per_format": per_format,
-        "transforms": transforms,
-        "sp_ell_row": sp_ell, "r_ell_row": r_ell,
-        "at_decision": {"table": os.path.relpath(table_path, ROOT) if table_path else None,
-                        "d_star": table.d_star if math.isfinite(table.d_star) else "inf",
-                        "choice": spmvat.FORMAT_NAMES[r0.decision[0]] if hasattr(r0, "decision") else None,
-                        "choice_k100": spmvat.FORMAT_NAMES[r0.decision_k100[0]] if hasattr(r0, "decision_k100") else None},
-        "precision": precision,
+        "transforms": h["transforms"],
+        "sp_ell_row": h["sp_ell_row"], "r_ell_row": h["r_ell_row"],
+        "at_decision": decision,
+        "precision": h["precision"],
         "kernel_source_sha": kernel_source_sha(),
     }
+    x64 = h.pop("x64")
+    if not args.no_extra and args.workload == "stencil27_128":
+        extra = {}
+        for name, steps in (("laplace64", args.steps), ("powerlaw", max(3, args.steps // 4))):
+            build_o, idx_o = builders[name]
+            t0 = time.time()
+            mo = build_o()
+            log(f"[bench] workload {mo.name}: n={mo.n} nnz={mo.nnz} generated in {time.time() - t0:.1f}s")
+            ho = measure(spmvat, mo, idx_o, steps, max(1, args.warmup // 2), args.spmv_reps, (), table, mo.name)
+            entry = {"workload": mo.name, "n": mo.n, "nnz": mo.nnz, "d_mat": ho["d_mat"], "ell_width": ho["w"],
+                     "steps": steps, "ms_per_step": round(ho["ms_per_step"], 3), "at_decision": ho["at_decision"]}
+            if name == "laplace64":
+                # 0.33 MB: cache-resident and launch-bound, latencies only
+                entry["spmv_median_us"] = {k: v["median_us"] for k, v in ho["per_format"].items()}
+                entry["transform_median_us"] = {k: v.get("median_us") for k, v in ho["transforms"].items()}
+            else:
+                entry["per_format"] = ho["per_format"]
+                entry["transforms"] = ho["transforms"]
+                entry["ell_row"] = "refused by the memory guard" if not ho["ell_row"] else "built"
+            extra[name] = entry
+            del ho, mo
+            torch.cuda.empty_cache()
+        out["workloads"] = extra
     if args.serve_jobs > 0:
         out["serving"] = serving(args.serve_jobs)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(m, x64, args.cpu_seconds, with_ell=r0.ell_row)
+        out["cpu_baseline"] = cpu_baseline(m, x64, args.cpu_seconds, with_ell=h["ell_row"])
     print(json.dumps(out), flush=True)
+
+
+def model_decision(path, h):
+    """The paper's rule with D* placed where the fitted D_mat - R_ell model
+    of the matrix's locality class crosses c (ELL-Row when D_mat is below
+    it and ELL-Row fits), beside this run's measured R_ell against the best
+    CRS kernel."""
+    if not path or not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        t = json.load(f)
+    local = h["bandwidth"] <= 65536
+    mdl = t.get("rd_model_vs_best_" + ("local" if local else "scattered")) or {}
+    cross = mdl.get("d_cross")
+    out = {"d_star_model": cross, "model_class": "local" if local else "scattered"}
+    if cross is not None:
+        out["choice_model"] = "ell_row" if (h["ell_row"] and h["d_mat"] < cross) else "crs"
+    if h.get("r_ell_row"):
+        out["r_ell_vs_crs_best_measured"] = h["r_ell_row"]["vs_crs_best"]
+    return out
+
+
+def table_matches_kernels(path):
+    """Whether the auto-tuning table was measured with the kernels built here
+    (its kernel_source_sha equals this tree's), or None without a stamp."""
+    if not path or not os.path.exists(path):
+        return None
+    import paper_2407_00019_amd as spmvat
+    with open(path) as f:
+        return spmvat.table_matches_kernels(json.load(f))
 
 
 def serving(count):
@@ -455,13 +572,8 @@ def cpu_model():
 
 
 def kernel_source_sha():
-    import hashlib
-    h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2407_00019_amd", "csrc"))):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(ROOT, "paper_2407_00019_amd", "csrc", f), "rb") as fh:
-                h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_2407_00019_amd import kernel_source_sha as sha
+    return sha()
 
 
 def cpu_baseline(m, x, budget_s, with_ell=True):
