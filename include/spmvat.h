@@ -398,7 +398,10 @@ void spmv_server_destroy(spmv_server *s);
 
 /* Host-only offset allocator of the server's arena, exported for callers
  * that sub-allocate one device block themselves: first fit, 256-byte
- * granularity, free neighbours coalesce.  Offsets, not pointers. */
+ * granularity, free neighbours coalesce.  Offsets, not pointers.  A size
+ * too large for the arena gets -1; spmv_arena_free takes back exactly what
+ * spmv_arena_alloc gave (same offset and size) and ignores a range outside
+ * the arena or overlapping free space.  Not thread-safe. */
 typedef struct spmv_arena spmv_arena;
 spmv_arena *spmv_arena_create(size_t bytes);
 int64_t spmv_arena_alloc(spmv_arena *a, size_t bytes);      /* offset, or -1 when no block fits */

@@ -482,13 +482,14 @@ def at_table_from_json(d: dict) -> at_table:
 
 
 def kernel_source_sha() -> str:
-    """Hash of the kernel sources (csrc/*.hip, *.h): a table or profile
-    measured with other kernels carries another value."""
+    """Hash of the kernel sources (csrc/*.hip, *.h, less the header of the
+    host-only code): a table or profile measured with other kernels carries
+    another value."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(_HERE, "csrc")
     for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
+        if f.endswith((".hip", ".h")) and f != "host_core.h":
             with open(os.path.join(d, f), "rb") as fh:
                 h.update(fh.read())
     return h.hexdigest()[:16]

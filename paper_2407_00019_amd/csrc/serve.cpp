@@ -36,71 +36,13 @@
 #include <vector>
 
 #include "../../include/spmvat.h"
+#include "host_core.h"
 #include "kernels.h"
 #include "plan_internal.h"
 
 #define SPMV_API extern "C" __attribute__((visibility("default")))
 
 using namespace spmvat;
-
-// ------------------------------------------------------------- arena
-
-struct spmv_arena {
-    // free blocks: offset -> size, kept coalesced
-    std::map<size_t, size_t> free_;
-    size_t cap = 0;
-    size_t free_bytes = 0;
-    static constexpr size_t kGrain = 256;
-
-    explicit spmv_arena(size_t bytes) : cap(bytes / kGrain * kGrain), free_bytes(cap) {
-        if (cap) free_[0] = cap;
-    }
-    static size_t round(size_t b) { return (std::max<size_t>(b, 1) + kGrain - 1) / kGrain * kGrain; }
-    int64_t alloc(size_t bytes) {
-        const size_t need = round(bytes);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= need) {
-                const size_t off = it->first, sz = it->second;
-                free_.erase(it);
-                if (sz > need) free_[off + need] = sz - need;
-                free_bytes -= need;
-                return (int64_t)off;
-            }
-        }
-        return -1;
-    }
-    void release(int64_t off, size_t bytes) {
-        size_t o = (size_t)off, sz = round(bytes);
-        free_bytes += sz;
-        auto next = free_.lower_bound(o);
-        if (next != free_.end() && o + sz == next->first) {
-            sz += next->second;
-            next = free_.erase(next);
-        }
-        if (next != free_.begin()) {
-            auto prev = std::prev(next);
-            if (prev->first + prev->second == o) {
-                prev->second += sz;
-                return;
-            }
-        }
-        free_[o] = sz;
-    }
-    size_t largest() const {
-        size_t m = 0;
-        for (auto& kv : free_) m = std::max(m, kv.second);
-        return m;
-    }
-};
-
-SPMV_API spmv_arena* spmv_arena_create(size_t bytes) { return new (std::nothrow) spmv_arena(bytes); }
-SPMV_API int64_t spmv_arena_alloc(spmv_arena* a, size_t bytes) { return a ? a->alloc(bytes) : -1; }
-SPMV_API void spmv_arena_free(spmv_arena* a, int64_t off, size_t bytes) {
-    if (a && off >= 0) a->release(off, bytes);
-}
-SPMV_API size_t spmv_arena_free_bytes(const spmv_arena* a) { return a ? a->free_bytes : 0; }
-SPMV_API size_t spmv_arena_largest(const spmv_arena* a) { return a ? a->largest() : 0; }
-SPMV_API void spmv_arena_destroy(spmv_arena* a) { delete a; }
 
 // ------------------------------------------------------------- server
 

@@ -314,3 +314,31 @@ def test_noalloc_coo_row_refuses_before_touching_the_gpu():
     assert f(8, -1, d, d, d, spmvat.F64, d, d, None) == spmvat.SPMV_E_ARG
     assert f(8, 8, d, d, d, 7, d, d, None) == spmvat.SPMV_E_ARG
     assert f(8, spmvat.COO_ROW_NOALLOC_MAX_NNZ + 1, d, d, d, spmvat.F32, d, d, None) == spmvat.SPMV_E_TOO_LARGE
+
+
+def test_arena_refuses_sizes_and_ranges_it_did_not_give():
+    """A size whose rounding would wrap, a second free of one block and a
+    range outside the arena leave the allocator unchanged."""
+    spmvat = _lib()
+    L = spmvat.lib()
+    cap = 1 << 16
+    A = L.spmv_arena_create(cap)
+    size_max = 2**64 - 1
+    assert L.spmv_arena_alloc(A, size_max) == -1
+    assert L.spmv_arena_alloc(A, size_max - 200) == -1
+    assert L.spmv_arena_alloc(A, cap + 1) == -1
+    o = L.spmv_arena_alloc(A, 1000)
+    assert o == 0 and L.spmv_arena_free_bytes(A) == cap - 1024
+    L.spmv_arena_free(A, o, 1000)
+    L.spmv_arena_free(A, o, 1000)            # already free: ignored
+    assert L.spmv_arena_free_bytes(A) == cap and L.spmv_arena_largest(A) == cap
+    a = L.spmv_arena_alloc(A, 512)
+    b = L.spmv_arena_alloc(A, 512)
+    assert (a, b) == (0, 512)
+    for off, size in ((-256, 256), (cap, 256), (cap - 256, 512), (0, size_max), (1024, 256)):
+        L.spmv_arena_free(A, off, size)      # outside the arena, or free space: ignored
+        assert L.spmv_arena_free_bytes(A) == cap - 1024
+    L.spmv_arena_free(A, b, 512)
+    L.spmv_arena_free(A, a, 512)
+    assert L.spmv_arena_free_bytes(A) == cap and L.spmv_arena_largest(A) == cap
+    L.spmv_arena_destroy(A)
