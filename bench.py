@@ -30,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COL_PAGED_MAX_BW = 32576   # the library's column SpMVs privatise y up to this bandwidth (spmvat.h)
 METRIC = "SpMV HBM GB/s (% peak) per format; transform time / CRS SpMV; jobs/s, p50/p99"
 
 
@@ -209,6 +210,9 @@ class PathRunner:
         if self.with_column and not spmv_only:
             T(f"{L}spmv_coo_col", sp.spmv_exec, plan, sp.COO_COL, 0, self.x, self.y, reps=R)
             T(f"{L}spmv_ell_col", sp.spmv_exec, plan, sp.ELL_COL, 0, self.x, self.y, reps=R)
+            # one atomic add per entry, for comparison with the default kernels
+            T(f"{L}spmv_coo_col_atomic", sp.spmv_exec, plan, sp.COO_COL, 1, self.x, self.y, reps=R)
+            T(f"{L}spmv_ell_col_atomic", sp.spmv_exec, plan, sp.ELL_COL, 1, self.x, self.y, reps=R)
         sp.spmv_plan_destroy(plan)
 
     def ccs_algorithms(self, reps=5):
@@ -325,7 +329,9 @@ def measure(spmvat, m, cfg_index, steps, warmup, spmv_reps, precision, table, lo
     spmv_names = {"crs_scalar": ("crs", "spmv_crs0", w), f"crs_subwave{wsub}": ("crs", f"spmv_crs{v_sub}", w),
                   "crs_stream": ("crs", "spmv_crs8", w),
                   "ell_row": ("ell_row", "spmv_ell_row", w), "coo_row": ("coo_row", "spmv_coo_row", w),
-                  "coo_col": ("coo_col", "spmv_coo_col", wc), "ell_col": ("ell_col", "spmv_ell_col", wc)}
+                  "coo_col": ("coo_col", "spmv_coo_col", wc), "ell_col": ("ell_col", "spmv_ell_col", wc),
+                  "coo_col_atomic": ("coo_col", "spmv_coo_col_atomic", wc),
+                  "ell_col_atomic": ("ell_col", "spmv_ell_col_atomic", wc)}
     # rates and ratios from the per-step medians (a host stall between two
     # events inflates one step's mean); "us" keeps the mean
     if not r0.ell_row:
@@ -389,7 +395,8 @@ def measure(spmvat, m, cfg_index, steps, warmup, spmv_reps, precision, table, lo
     for r in runners:
         r.release()
     del runners
-    return {"m": m, "n": n, "nnz": nnz, "w": w, "wsub": wsub, "d_mat": r0.stats.d_mat, "ms_per_step": ms_per_step,
+    return {"m": m, "n": n, "nnz": nnz, "w": w, "wc": wc, "wsub": wsub, "d_mat": r0.stats.d_mat,
+            "ms_per_step": ms_per_step,
             "bandwidth": r0.stats.bandwidth,
             "per_format": per_format, "best": best, "transforms": transforms, "sp_ell_row": sp_ell,
             "r_ell_row": r_ell, "precision": prec, "at_decision": decision, "x64": x64, "ell_row": r0.ell_row}
@@ -448,11 +455,17 @@ def main():
     head = per_format[best]
     wsub = h["wsub"]
     ell2 = f"k_spmv_ell_row2<double, double, {w if 0 < w <= 32 else 0}>"   # widths 1..32 are unrolled kernels
+    wc = h["wc"]
+    paged = 0 <= h["bandwidth"] <= COL_PAGED_MAX_BW   # the column SpMVs' default kernels
     kernel_names = {"ell_row": ell2 if n % 2 == 0 else "k_spmv_ell_row<double, double>",
                     f"crs_subwave{wsub}": f"k_spmv_crs_vector<double, double, {wsub}>",
                     "crs_stream": f"k_spmv_crs_stream<double, double, {stream_lanes(n, nnz)}>",
                     "crs_scalar": "k_spmv_crs_scalar<double, double>", "coo_row": "k_spmv_coo_row<double, double>",
-                    "coo_col": "k_spmv_coo_col<double, double>", "ell_col": "k_spmv_ell_col<double, double>"}
+                    "coo_col": "k_spmv_coo_col_pg<double, double>" if paged else "k_spmv_coo_col<double, double>",
+                    "ell_col": (f"k_spmv_ell_col_pg<double, double, {'true' if wc <= 32 else 'false'}>" if paged
+                                else "k_spmv_ell_col<double, double>"),
+                    "coo_col_atomic": "k_spmv_coo_col<double, double>",
+                    "ell_col_atomic": "k_spmv_ell_col<double, double>"}
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tpath):

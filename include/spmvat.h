@@ -248,15 +248,21 @@ spmv_status csr_to_ell(spmv_plan *p, int column_wise, const spmv_buffers *out,
 /* y = A x (overwrites y; the paper's loops accumulate into a cleared Y) in
  * format f (section 3, Figs. 1-3, and CRS itself).  x[n] and y[n] are
  * device arrays: F64 for F64 values, else F32 (accumulation in F32).
- * variant (CRS only): 0 one thread per row (the plain CRS loop); 1 the
+ * variant, CRS: 0 one thread per row (the plain CRS loop); 1 the
  * library's CRS kernel, currently the stream kernel; 2..7 a group of
  * 2^(variant-1) lanes per row; 8 the stream kernel (a workgroup stages the
  * products of 256/G consecutive rows in LDS and G lanes sum each row, G from
  * the mean row length and n; with G = 1 a thread sums its row in storage
  * order; the workgroup reduces rows of more than 256 entries).
- * Other formats take variant 0; ELL_ROW splits a row's slots over several
- * threads (the outer-parallel form of Fig. 4) when n is too small to fill
- * the GPU with one thread per row.
+ * variant, COO_COL and ELL_COL (Fig. 1's private copies of Y): 1 one atomic
+ * add into y per entry; 2 a workgroup sums its entries into LDS partial
+ * sums for the rows it touches (pages of 64 rows of its window of rows,
+ * [first column - bandwidth, last column + bandwidth]) and adds each sum
+ * into y once; 0 takes 2 when the matrix bandwidth is at most 32,576 (every
+ * window fits the page table), else 1.
+ * COO_ROW and ELL_ROW take variant 0; ELL_ROW splits a row's slots over
+ * several threads (the outer-parallel form of Fig. 4) when n is too small to
+ * fill the GPU with one thread per row.
  * Determinism: CRS, COO_ROW and ELL_ROW are deterministic run to run;
  * COO_COL and ELL_COL scatter with atomics and are not.  x and y must not
  * overlap.  SPMV_E_NOT_READY when the format has not been built. */
@@ -374,7 +380,10 @@ typedef struct {
     int64_t id;
     int32_t status;            /* spmv_status of the job */
     int32_t format, variant;   /* format used (-1 if never admitted) */
-    double arrival_s, admit_s, ready_s, done_s;   /* seconds after start */
+    /* seconds after start: arrival; admission (CRS and vector blocks
+     * allocated); ready (format built, handed to the engine); done (result
+     * copied back, the job's memory given back) */
+    double arrival_s, admit_s, ready_s, done_s;
     double d_mat;
     size_t device_bytes;       /* arena bytes the job held */
 } spmv_job_result;

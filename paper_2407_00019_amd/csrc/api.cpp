@@ -545,6 +545,18 @@ SPMV_API spmv_status csr_to_ell(spmv_plan* p, int column_wise, const spmv_buffer
 
 // ------------------------------------------------------------------ SpMV
 
+namespace {
+
+// Column SpMV kernel of a variant: 1 one global atomic per entry, 2 y
+// privatised in LDS by pages; 0 takes 2 when the bandwidth lets every
+// workgroup's row window fit the page table.
+int col_variant(const spmv_plan* p, int variant) {
+    if (variant != 0) return variant;
+    return col_paged_fits(p->n, p->st.bandwidth) ? 2 : 1;
+}
+
+}  // namespace
+
 spmv_status spmvat::plan_exec(const spmv_plan* p, spmv_format f, int variant, const void* x, void* y,
                               double alpha, hipStream_t s) {
     if (!p || !x || !y || !aligned16(x) || !aligned16(y)) return SPMV_E_ARG;
@@ -576,13 +588,22 @@ spmv_status spmvat::plan_exec(const spmv_plan* p, spmv_format f, int variant, co
             HIP_TRY(p, launch_spmv_ell_row(dt, p->n, p->ell_w, p->ell_val, p->ell_col, x, y, alpha, s));
             return SPMV_OK;
         case SPMV_ELL_COL:
-            if (variant != 0) return SPMV_E_ARG;
+            if (variant < 0 || variant > 2) return SPMV_E_ARG;
             if (p->ellc_w < 0) return SPMV_E_NOT_READY;
-            HIP_TRY(p, launch_spmv_ell_col(dt, p->n, p->ellc_w, p->ellc_val, p->ellc_row, x, y, s));
+            if (col_variant(p, variant) == 2)
+                HIP_TRY(p, launch_spmv_ell_col_paged(dt, p->n, p->ellc_w, p->st.bandwidth, p->ellc_val, p->ellc_row,
+                                                     x, y, s));
+            else
+                HIP_TRY(p, launch_spmv_ell_col(dt, p->n, p->ellc_w, p->ellc_val, p->ellc_row, x, y, s));
             return SPMV_OK;
         case SPMV_COO_COL:
-            if (variant != 0) return SPMV_E_ARG;
+            if (variant < 0 || variant > 2) return SPMV_E_ARG;
             if (!p->has_coo_col || !p->has_ccs) return SPMV_E_NOT_READY;
+            if (col_variant(p, variant) == 2) {
+                HIP_TRY(p, launch_spmv_coo_col_paged(dt, p->n, p->nnz, p->st.bandwidth, p->jcol, p->irow_t, p->val_t,
+                                                     x, y, s));
+                return SPMV_OK;
+            }
             HIP_TRY(p, launch_fill_zero(y, ybytes, s));
             if (p->nnz > 0)
                 HIP_TRY(p, launch_spmv_coo_col(dt, p->nnz, p->jcol, p->irow_t, p->val_t, x, y, s));

@@ -133,6 +133,15 @@ hipError_t launch_spmv_coo_row(int dtype, int n, int64_t nnz, const int* irow, c
                                const void* val, const void* x, void* y, void* carries, hipStream_t s);
 hipError_t launch_spmv_coo_col(int dtype, int64_t nnz, const int* jcol, const int* irow_t,
                                const void* val_t, const void* x, void* y, hipStream_t s);
+// Column SpMVs with y privatised in LDS by pages of 64 rows (bw = the
+// matrix bandwidth, max |i - j|).  Both clear y first.  Correct for any bw;
+// they pay off when col_paged_fits(n, bw): then every ELL-Column
+// workgroup's row window fits the page table.
+bool col_paged_fits(int n, int bw);
+hipError_t launch_spmv_ell_col_paged(int dtype, int n, int width, int bw, const void* ev, const int* er,
+                                     const void* x, void* y, hipStream_t s);
+hipError_t launch_spmv_coo_col_paged(int dtype, int n, int64_t nnz, int bw, const int* jcol, const int* irow_t,
+                                     const void* val_t, const void* x, void* y, hipStream_t s);
 size_t coo_carry_bytes(int64_t nnz);
 // COO-Row SpMV with its carries in a fixed per-device array (no workspace):
 // y is cleared first, then the same kernels as launch_spmv_coo_row run.

@@ -213,7 +213,6 @@ struct spmv_server {
     spmv_status prepare(Slot& s, JobState& js) {
         spmv_status st = plan_finish(&js.plan, *s.host_stats);
         if (st != SPMV_OK) return st;
-        js.res.ready_s = now();
         js.res.d_mat = js.plan.st.d_mat;
         spmv_format f = SPMV_CRS;
         int v = 1;
@@ -275,6 +274,7 @@ struct spmv_server {
         // a job whose step alone exceeds a tick's work items could never run
         const int64_t items = ((int64_t)js.job.n + js.rows_per_item - 1) / js.rows_per_item;
         if (items > ((int64_t)kMaxCoarse << kServeCoarseBits)) return SPMV_E_TOO_LARGE;
+        js.res.ready_s = now();   // its format is built: the job goes to the engine
         return SPMV_OK;
     }
 

@@ -54,6 +54,9 @@ def arrow(n, seed, dense_cols=(0,), mid_col=None, mid_len=1000):
 SMALL += [
     ("arrow_mid", lambda: arrow(3000, 9, dense_cols=(5,), mid_col=77, mid_len=700)),
     ("arrow_long", lambda: arrow(50000, 10, dense_cols=(0, 49999), mid_col=123, mid_len=5000)),
+    # bandwidth ~ n = 100,000: every column workgroup's row window is wider
+    # than the page table, so the paged column kernels fall back per workgroup
+    ("wide_sparse", lambda: gen.random_small(100000, 7, 3, True, False, 0.1, integer_values=False)),
 ]
 
 
@@ -74,7 +77,8 @@ def run_gpu_all(m, x64):
     ys = {}
     for fmt, var in [(spmvat.CRS, 0), (spmvat.CRS, 1), (spmvat.CRS, 2), (spmvat.CRS, 4), (spmvat.CRS, 6),
                      (spmvat.CRS, 7), (spmvat.CRS, 8), (spmvat.COO_ROW, 0), (spmvat.ELL_ROW, 0),
-                     (spmvat.COO_COL, 0), (spmvat.ELL_COL, 0)]:
+                     (spmvat.COO_COL, 0), (spmvat.COO_COL, 1), (spmvat.COO_COL, 2),
+                     (spmvat.ELL_COL, 0), (spmvat.ELL_COL, 1), (spmvat.ELL_COL, 2)]:
         ys[(fmt, var)] = host(plan.spmv(fmt, xd, variant=var))
     out["y"] = ys
     out = {k: (host(v) if hasattr(v, "cpu") else v) for k, v in out.items()}
@@ -211,7 +215,7 @@ def test_powerlaw_full_size():
     assert np.array_equal(host(cr), o_cr)
     yref = oracle.spmv_crs(m.n, m.irp, m.icol, m.val, x)
     for fmt, var in [(spmvat.CRS, 0), (spmvat.CRS, 1), (spmvat.CRS, 5), (spmvat.CRS, 8), (spmvat.COO_ROW, 0),
-                     (spmvat.COO_COL, 0), (spmvat.ELL_COL, 0)]:
+                     (spmvat.COO_COL, 0), (spmvat.COO_COL, 2), (spmvat.ELL_COL, 0), (spmvat.ELL_COL, 2)]:
         y = host(plan.spmv(fmt, xd, variant=var))
         assert oracle.rel_l2(y, yref) <= TOL64, (fmt, var)
     plan.close()

@@ -73,7 +73,8 @@ def test_reduced_precision_path(name, builder, dt, dname):
     absref = oracle.spmv_crs(n, m.irp, m.icol, np.abs(vw), np.abs(xw))
     lens = np.diff(m.irp)
     for fmt, var in [(spmvat.CRS, 0), (spmvat.CRS, 1), (spmvat.CRS, 5), (spmvat.CRS, 8), (spmvat.COO_ROW, 0),
-                     (spmvat.ELL_ROW, 0), (spmvat.COO_COL, 0), (spmvat.ELL_COL, 0)]:
+                     (spmvat.ELL_ROW, 0), (spmvat.COO_COL, 0), (spmvat.COO_COL, 1), (spmvat.COO_COL, 2),
+                     (spmvat.ELL_COL, 0), (spmvat.ELL_COL, 1), (spmvat.ELL_COL, 2)]:
         y = plan.spmv(fmt, xd, variant=var)
         assert y.dtype == torch.float32
         ok = higham_ok(host(y), yref, absref, lens)
