@@ -30,7 +30,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-COL_PAGED_MAX_BW = 32576   # the library's column SpMVs privatise y up to this bandwidth (spmvat.h)
+# the library's column SpMVs privatise y up to this bandwidth (spmvat.h)
+def col_paged_max_bw(n):
+    return 32192 if n % 4 == 0 else 32576
 METRIC = "SpMV HBM GB/s (% peak) per format; transform time / CRS SpMV; jobs/s, p50/p99"
 
 
@@ -456,13 +458,14 @@ def main():
     wsub = h["wsub"]
     ell2 = f"k_spmv_ell_row2<double, double, {w if 0 < w <= 32 else 0}>"   # widths 1..32 are unrolled kernels
     wc = h["wc"]
-    paged = 0 <= h["bandwidth"] <= COL_PAGED_MAX_BW   # the column SpMVs' default kernels
+    paged = 0 <= h["bandwidth"] <= col_paged_max_bw(n)   # the column SpMVs' default kernels
     kernel_names = {"ell_row": ell2 if n % 2 == 0 else "k_spmv_ell_row<double, double>",
                     f"crs_subwave{wsub}": f"k_spmv_crs_vector<double, double, {wsub}>",
                     "crs_stream": f"k_spmv_crs_stream<double, double, {stream_lanes(n, nnz)}>",
                     "crs_scalar": "k_spmv_crs_scalar<double, double>", "coo_row": "k_spmv_coo_row<double, double>",
                     "coo_col": "k_spmv_coo_col_pg<double, double>" if paged else "k_spmv_coo_col<double, double>",
-                    "ell_col": (f"k_spmv_ell_col_pg<double, double, {'true' if wc <= 32 else 'false'}>" if paged
+                    "ell_col": (("k_spmv_ell_col_pg<double, double, 4, 32768>" if n % 4 == 0
+                                 else "k_spmv_ell_col_pg<double, double, 1, 20480>") if paged
                                 else "k_spmv_ell_col<double, double>"),
                     "coo_col_atomic": "k_spmv_coo_col<double, double>",
                     "ell_col_atomic": "k_spmv_ell_col<double, double>"}

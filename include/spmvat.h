@@ -258,8 +258,9 @@ spmv_status csr_to_ell(spmv_plan *p, int column_wise, const spmv_buffers *out,
  * add into y per entry; 2 a workgroup sums its entries into LDS partial
  * sums for the rows it touches (pages of 64 rows of its window of rows,
  * [first column - bandwidth, last column + bandwidth]) and adds each sum
- * into y once; 0 takes 2 when the matrix bandwidth is at most 32,576 (every
- * window fits the page table), else 1.
+ * into y once; 0 takes 2 when every workgroup's window fits the page table
+ * (matrix bandwidth at most 32,192, or 32,576 when n is not a multiple of
+ * 4), else 1.
  * COO_ROW and ELL_ROW take variant 0; ELL_ROW splits a row's slots over
  * several threads (the outer-parallel form of Fig. 4) when n is too small to
  * fill the GPU with one thread per row.

@@ -3,12 +3,14 @@
 // bandwidth: the GPU form of the figures' private copies of Y, restricted
 // to the rows a workgroup actually touches.
 //
-// A workgroup owns 256 consecutive columns (ELL-Column) or 8192 consecutive
-// entries (COO-Column).  Every row its entries add into lies in the window
+// A workgroup owns 1024 consecutive columns (ELL-Column, 4 adjacent columns
+// per thread, vector loads; 256 columns when n is not a multiple of 4) or
+// 4096 consecutive entries (COO-Column, 4 consecutive entries per thread and
+// step).  Every row its entries add into lies in the window
 // [first column - bw, last column + bw], bw = max |i - j|.  The window is
 // cut into pages of 64 rows.  The workgroup
 //   1. marks the pages its entries touch (only the first lane of each run
-//      of equal pages in a wave stores the mark),
+//      of equal pages in a row of 16 lanes stores the mark),
 //   2. numbers the marked pages with a scan: page k gets partial-sum slot k,
 //   3. adds each product into its row's LDS partial sum (LDS atomics),
 //   4. adds every non-zero partial sum into y with one global atomic.
@@ -18,6 +20,12 @@
 // capacity, and whole workgroups whose window is too wide, add straight
 // into y.  y is cleared first; the order of the additions depends on
 // scheduling, as with the per-entry kernels.
+//
+// Sizes measured on the 27-point 128^3 stencil (binary64): ELL-Column with
+// 1, 2 and 4 columns per thread took 224, 198 and 180 us (4 columns with
+// fewer than 64 partial-sum pages spill past the capacity: 240-450 us);
+// COO-Column with 8192-, 4096- and 2048-entry chunks of single entries took
+// 344, 309 and 334 us, 4096 entries as pairs 256 us and as quads 237 us.
 #include "common.h"
 #include "kernels.h"
 
@@ -28,16 +36,21 @@ namespace {
 constexpr int kPgBits = 6;
 constexpr int kPgRows = 1 << kPgBits;        // rows per page
 constexpr int kPgWindow = 1024;              // pages of a window: 65,536 rows
-constexpr int kPgAccBytes = 20480;           // LDS partial sums: 40 binary64 or 80 binary32 pages
-constexpr int kEcCache = 32;                 // ELL-Column: widths whose rows stay in registers
-constexpr int kCcChunk = 8192;               // COO-Column: entries per workgroup
-constexpr int kCcPer = kCcChunk / kBlock;    // 32 per thread
 constexpr int kPgPer = kPgWindow / kBlock;   // window pages per thread in the numbering scan
 static_assert(kPgWindow % kBlock == 0, "the numbering scan gives each thread whole pages");
+constexpr int kEcVec = 4;                    // ELL-Column: adjacent columns per thread (n % 4 == 0)
+constexpr int kEcAccBytes = 32768;           // its partial sums: 64 binary64 / 128 binary32 pages
+constexpr int kEc1AccBytes = 20480;          // one column per thread: 40 / 80 pages
+constexpr int kCcVec = 4;                    // COO-Column: consecutive entries per thread and step
+constexpr int kCcChunk = 4096;               // entries per workgroup
+constexpr int kCcSteps = kCcChunk / (kCcVec * kBlock);
+constexpr int kCcAccBytes = 16384;           // its partial sums: 32 binary64 / 64 binary32 pages
+static_assert(kCcChunk % (kCcVec * kBlock) == 0, "a chunk is whole steps");
 
-template <typename X>
+template <typename X, int kBytes>
 struct PgSmem {
-    static constexpr int kCap = kPgAccBytes / (int)sizeof(X) / kPgRows;   // pages that get a partial sum
+    using Acc = X;
+    static constexpr int kCap = kBytes / (int)sizeof(X) / kPgRows;   // pages that get a partial sum
     X acc[kCap * kPgRows];
     int slot[kPgWindow];        // per window page: 1 when marked, then its slot or -1
     int page_of[kCap];          // window page of each slot
@@ -53,12 +66,15 @@ __device__ __forceinline__ void add_lds(X* p, X v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Marks window page pg (< 0: nothing).  Every lane of the wave calls it; a
-// lane stores only when the lane below it holds another page.
+// Marks window page pg (< 0: nothing).  Every lane of the wave calls it,
+// all active.  A lane stores only when the lane below it in its row of 16
+// lanes (a DPP row shift, no LDS traffic) holds another page; the first
+// lane of each row always stores, so every page held by some lane is
+// marked.
 __device__ __forceinline__ void mark_page(int* slot, int pg) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int below = __shfl_up(pg, 1, kWave);
-    if (pg >= 0 && (lane == 0 || below != pg))
+    constexpr int kRowShr1 = 0x111;
+    const int below = __builtin_amdgcn_update_dpp(-2, pg, kRowShr1, 0xf, 0xf, false);
+    if (pg >= 0 && below != pg)
         __hip_atomic_store(&slot[pg], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
@@ -66,8 +82,8 @@ __device__ __forceinline__ void mark_page(int* slot, int pg) {
 // (-1 for unmarked pages and for marked pages past the capacity), fills
 // page_of and returns the number of slots used.  Starts and ends with a
 // barrier.
-template <typename X>
-__device__ __forceinline__ int number_pages(PgSmem<X>& sm, int nwin) {
+template <class S>
+__device__ __forceinline__ int number_pages(S& sm, int nwin) {
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
     __syncthreads();
     int m[kPgPer];
@@ -98,7 +114,7 @@ __device__ __forceinline__ int number_pages(PgSmem<X>& sm, int nwin) {
         if (pg >= nwin) continue;
         int v = -1;
         if (m[e]) {
-            if (s < PgSmem<X>::kCap) {
+            if (s < S::kCap) {
                 v = s;
                 sm.page_of[s] = pg;
             }
@@ -107,12 +123,12 @@ __device__ __forceinline__ int number_pages(PgSmem<X>& sm, int nwin) {
         sm.slot[pg] = v;
     }
     __syncthreads();
-    return min(total, PgSmem<X>::kCap);
+    return min(total, S::kCap);
 }
 
-template <typename X>
-__device__ __forceinline__ void clear_acc(PgSmem<X>& sm, int used) {
-    for (int t = threadIdx.x; t < used * kPgRows; t += kBlock) sm.acc[t] = (X)0;
+template <class S>
+__device__ __forceinline__ void clear_acc(S& sm, int used) {
+    for (int t = threadIdx.x; t < used * kPgRows; t += kBlock) sm.acc[t] = (typename S::Acc)0;
     __syncthreads();
 }
 
@@ -123,8 +139,8 @@ __device__ __forceinline__ int page_in(int r, int lo, int nwin) {
 }
 
 // Adds v into row r: its LDS partial sum when its page has a slot, else y.
-template <typename X>
-__device__ __forceinline__ void add_row(PgSmem<X>& sm, int lo, int nwin, int r, X v, X* y) {
+template <class S, typename X>
+__device__ __forceinline__ void add_row(S& sm, int lo, int nwin, int r, X v, X* y) {
     const int pg = page_in(r, lo, nwin);
     const int s = pg >= 0 ? sm.slot[pg] : -1;
     if (s >= 0) add_lds(&sm.acc[s * kPgRows + ((r - lo) & (kPgRows - 1))], v);
@@ -134,8 +150,8 @@ __device__ __forceinline__ void add_row(PgSmem<X>& sm, int lo, int nwin, int r, 
 // One global atomic per row whose partial sum is not zero (a row that got
 // no product keeps +0.0, and adding +0.0 would change nothing).  Starts
 // with a barrier.
-template <typename X>
-__device__ __forceinline__ void flush(PgSmem<X>& sm, int used, int lo, X* y) {
+template <class S, typename X>
+__device__ __forceinline__ void flush(S& sm, int used, int lo, X* y) {
     __syncthreads();
     for (int t = threadIdx.x; t < used * kPgRows; t += kBlock) {
         const X a = sm.acc[t];
@@ -151,80 +167,100 @@ __device__ __forceinline__ void window(int n, int64_t first, int64_t last, int b
     nwin = (int)((b - a + kPgRows - 1) >> kPgBits);
 }
 
+// C consecutive indices (C = 1 or 4; p aligned to 4 C bytes).
+template <int C>
+__device__ __forceinline__ void load_idx(const int* p, int (&r)[C]) {
+    if constexpr (C == 4) {
+        const int4 v = *reinterpret_cast<const int4*>(p);
+        r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w;
+    } else {
+        r[0] = p[0];
+    }
+}
+
+// C consecutive values through non-temporal loads (p aligned to C values).
+template <typename V, int C>
+__device__ __forceinline__ void load_val(const V* p, V (&v)[C]) {
+    if constexpr (C == 4) {
+        load2_nt(p, v[0], v[1]);
+        load2_nt(p + 2, v[2], v[3]);
+    } else {
+        v[0] = ld_nt(p);
+    }
+}
+
 }  // namespace
 
-// ELL-Column: thread t of workgroup b takes column 256 b + t and walks its
-// slots.  With kCache the rows of up to kEcCache slots stay in registers
-// between the marking and the adding pass; otherwise they are read twice.
-template <typename V, typename X, bool kCache>
+// ELL-Column: thread t of workgroup b takes the C adjacent columns
+// C (256 b + t) .. + C-1 and walks their slots twice: the first pass loads
+// the rows and marks their pages, the second loads rows and values again
+// and adds.  C = 4 needs n % 4 == 0 (every slot's column group aligned).
+// Padding slots (value +0.0) add nothing.
+template <typename V, typename X, int C, int kBytes>
 __global__ void __launch_bounds__(kBlock)
 k_spmv_ell_col_pg(int n, int width, int bw, const V* __restrict__ ev, const int* __restrict__ er,
                   const X* __restrict__ x, X* __restrict__ y) {
-    __shared__ PgSmem<X> sm;
-    const int j0 = (int)xcd_block(blockIdx.x, gridDim.x) * kBlock;
-    const int j = j0 + (int)threadIdx.x;
+    __shared__ PgSmem<X, kBytes> sm;
+    const int j0 = (int)xcd_block(blockIdx.x, gridDim.x) * (C * kBlock);
+    const int j = j0 + C * (int)threadIdx.x;
     const bool live = j < n;
     int lo, nwin;
-    window(n, j0, min((int64_t)n, (int64_t)j0 + kBlock) - 1, bw, lo, nwin);
+    window(n, j0, min((int64_t)n, (int64_t)j0 + C * kBlock) - 1, bw, lo, nwin);
     if (nwin > kPgWindow) {
         // window too wide for the page table: one global atomic per entry
         if (!live) return;
-        const X xj = x[j];
-        size_t off = (size_t)j;
-        for (int k = 0; k < width; ++k, off += (size_t)n) {
-            const X v = (X)widen(ld_nt(&ev[off]));
-            if (v != (X)0) add_global(&y[er[off]], v * xj);
+        for (int c = 0; c < C; ++c) {
+            const X xj = x[j + c];
+            size_t off = (size_t)j + c;
+            for (int k = 0; k < width; ++k, off += (size_t)n) {
+                const X v = (X)widen(ld_nt(&ev[off]));
+                if (v != (X)0) add_global(&y[er[off]], v * xj);
+            }
         }
         return;
     }
     for (int pg = threadIdx.x; pg < nwin; pg += kBlock) sm.slot[pg] = 0;
     __syncthreads();
-    int rows[kCache ? kEcCache : 1];
-    if constexpr (kCache) {
+    size_t off = (size_t)j;
+    for (int k = 0; k < width; ++k, off += (size_t)n) {
+        int r[C];
 #pragma unroll
-        for (int k = 0; k < kEcCache; ++k) {
-            rows[k] = -1;
-            if (k < width) {
-                rows[k] = live ? er[(size_t)k * n + j] : -1;
-                mark_page(sm.slot, live ? page_in(rows[k], lo, nwin) : -1);
-            }
-        }
-    } else {
-        size_t off = (size_t)j;
-        for (int k = 0; k < width; ++k, off += (size_t)n) {
-            mark_page(sm.slot, live ? page_in(er[off], lo, nwin) : -1);
-        }
+        for (int c = 0; c < C; ++c) r[c] = -1;
+        if (live) load_idx<C>(&er[off], r);
+#pragma unroll
+        for (int c = 0; c < C; ++c) mark_page(sm.slot, page_in(r[c], lo, nwin));
     }
     const int used = number_pages(sm, nwin);
     clear_acc(sm, used);
     if (live) {
-        const X xj = x[j];
-        if constexpr (kCache) {
+        X xs[C];
 #pragma unroll
-            for (int k = 0; k < kEcCache; ++k) {
-                if (k < width) {
-                    const X v = (X)widen(ld_nt(&ev[(size_t)k * n + j]));
-                    if (v != (X)0) add_row(sm, lo, nwin, rows[k], v * xj, y);
-                }
-            }
-        } else {
-            size_t off = (size_t)j;
-            for (int k = 0; k < width; ++k, off += (size_t)n) {
-                const X v = (X)widen(ld_nt(&ev[off]));
-                if (v != (X)0) add_row(sm, lo, nwin, er[off], v * xj, y);
+        for (int c = 0; c < C; ++c) xs[c] = x[j + c];
+        off = (size_t)j;
+        for (int k = 0; k < width; ++k, off += (size_t)n) {
+            int r[C];
+            V v[C];
+            load_idx<C>(&er[off], r);
+            load_val<V, C>(&ev[off], v);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const X w = (X)widen(v[c]);
+                if (w != (X)0) add_row(sm, lo, nwin, r[c], w * xs[c], y);
             }
         }
     }
     flush(sm, used, lo, y);
 }
 
-// COO-Column: workgroup b takes entries [8192 b, 8192 (b+1)); thread t holds
-// entries 256 e + t, e < 32, whose rows stay in registers.
+// COO-Column: workgroup b takes entries [4096 b, 4096 (b+1)); at step e
+// thread t holds the 4 consecutive entries 4 (256 e + t) .. + 3, loaded as
+// vectors, and keeps their rows in registers between the passes.
 template <typename V, typename X>
 __global__ void __launch_bounds__(kBlock)
 k_spmv_coo_col_pg(int n, int64_t nnz, int bw, const int* __restrict__ jcol, const int* __restrict__ irow_t,
                   const V* __restrict__ val_t, const X* __restrict__ x, X* __restrict__ y) {
-    __shared__ PgSmem<X> sm;
+    constexpr int C = kCcVec;
+    __shared__ PgSmem<X, kCcAccBytes> sm;
     const int64_t t0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kCcChunk;
     const int cnt = (int)min((int64_t)kCcChunk, nnz - t0);
     const int tid = threadIdx.x;
@@ -238,27 +274,48 @@ k_spmv_coo_col_pg(int n, int64_t nnz, int bw, const int* __restrict__ jcol, cons
     }
     for (int pg = tid; pg < nwin; pg += kBlock) sm.slot[pg] = 0;
     __syncthreads();
-    int rows[kCcPer];
+    int rows[kCcSteps][C];
 #pragma unroll
-    for (int e = 0; e < kCcPer; ++e) {
-        const int q = e * kBlock + tid;
-        rows[e] = q < cnt ? irow_t[t0 + q] : -1;
-        mark_page(sm.slot, q < cnt ? page_in(rows[e], lo, nwin) : -1);
+    for (int e = 0; e < kCcSteps; ++e) {
+        const int q = C * (e * kBlock + tid);
+#pragma unroll
+        for (int c = 0; c < C; ++c) rows[e][c] = -1;
+        if (q + C <= cnt) {
+            load_idx<C>(&irow_t[t0 + q], rows[e]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (q + c < cnt) rows[e][c] = irow_t[t0 + q + c];
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) mark_page(sm.slot, page_in(rows[e][c], lo, nwin));
     }
     const int used = number_pages(sm, nwin);
     clear_acc(sm, used);
 #pragma unroll
-    for (int e = 0; e < kCcPer; ++e) {
-        const int q = e * kBlock + tid;
-        if (q < cnt) add_row(sm, lo, nwin, rows[e], (X)widen(ld_nt(&val_t[t0 + q])) * x[jcol[t0 + q]], y);
+    for (int e = 0; e < kCcSteps; ++e) {
+        const int q = C * (e * kBlock + tid);
+        if (q + C <= cnt) {
+            V v[C];
+            int col[C];
+            load_val<V, C>(&val_t[t0 + q], v);
+            load_idx<C>(&jcol[t0 + q], col);
+#pragma unroll
+            for (int c = 0; c < C; ++c) add_row(sm, lo, nwin, rows[e][c], (X)widen(v[c]) * x[col[c]], y);
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (q + c < cnt)
+                    add_row(sm, lo, nwin, rows[e][c], (X)widen(val_t[t0 + q + c]) * x[jcol[t0 + q + c]], y);
+        }
     }
     flush(sm, used, lo, y);
 }
 
 bool col_paged_fits(int n, int bw) {
     // every ELL-Column workgroup's window fits the page table
-    (void)n;
-    return bw >= 0 && (int64_t)kBlock + 2 * (int64_t)bw + 2 * kPgRows <= (int64_t)kPgWindow * kPgRows;
+    const int cols = (n % kEcVec == 0 ? kEcVec : 1) * kBlock;
+    return bw >= 0 && (int64_t)cols + 2 * (int64_t)bw + 2 * kPgRows <= (int64_t)kPgWindow * kPgRows;
 }
 
 #define COLPG_DISPATCH(dtype, CALL)                                  \
@@ -274,13 +331,14 @@ hipError_t launch_spmv_ell_col_paged(int dtype, int n, int width, int bw, const 
     const int xb = dtype == 0 ? 8 : 4;
     hipError_t e = launch_fill_zero(y, (int64_t)n * xb, s);
     if (e != hipSuccess || width == 0) return e;
-    const dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
-    if (width <= kEcCache) {
-        COLPG_DISPATCH(dtype, hipLaunchKernelGGL((k_spmv_ell_col_pg<V, X, true>), grid, dim3(kBlock), 0, s, n,
-                                                 width, bw, (const V*)ev, er, (const X*)x, (X*)y));
+    if (n % kEcVec == 0) {
+        const dim3 grid((unsigned)(n / (kEcVec * kBlock) + (n % (kEcVec * kBlock) != 0)));
+        COLPG_DISPATCH(dtype, hipLaunchKernelGGL((k_spmv_ell_col_pg<V, X, kEcVec, kEcAccBytes>), grid, dim3(kBlock),
+                                                 0, s, n, width, bw, (const V*)ev, er, (const X*)x, (X*)y));
     } else {
-        COLPG_DISPATCH(dtype, hipLaunchKernelGGL((k_spmv_ell_col_pg<V, X, false>), grid, dim3(kBlock), 0, s, n,
-                                                 width, bw, (const V*)ev, er, (const X*)x, (X*)y));
+        const dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
+        COLPG_DISPATCH(dtype, hipLaunchKernelGGL((k_spmv_ell_col_pg<V, X, 1, kEc1AccBytes>), grid, dim3(kBlock), 0, s,
+                                                 n, width, bw, (const V*)ev, er, (const X*)x, (X*)y));
     }
     return hipGetLastError();
 }
