@@ -40,10 +40,12 @@ constexpr int kBcCols = 1 << kBcBits;
 constexpr int kBcRows = 2048;              // rows per tile
 constexpr int kBcWaves = 16;               // waves per tile (count, distribute)
 constexpr int kBcThreads = kBcWaves * kWave;
-constexpr int kBcUnroll = 4;               // groups of 64 entries loaded ahead
+constexpr int kBcUnroll = 8;               // groups of 64 entries loaded ahead
 constexpr int kPlWaves = 8;                // place: waves per block
 constexpr int kPlThreads = kPlWaves * kWave;
 constexpr int kPlStageBytes = 36 * 1024;   // place: LDS stage of rows and values
+constexpr int kPlBlocks = 4;               // place: blocks per workgroup
+constexpr int kPlPer = 4;                  // place: entries per lane and block held in registers
 constexpr int kBcMaxWindowBlocks = 1536;   // count / distribute LDS: 16 waves x 1536 counters = 96 KiB
 
 __device__ __forceinline__ int bc_lo(int t, int bw) { return max(0, t * kBcRows - bw); }
@@ -206,97 +208,165 @@ k_bcs_distribute(int n, int bw, int nwbmax, int wb_bits, const int* __restrict__
 // ------------------------------------------------------------------ place
 
 template <typename V>
-__global__ void __launch_bounds__(kPlThreads)
-k_bcs_place(int n, int nb, const int* __restrict__ bstart, const uint32_t* __restrict__ key,
-            const V* __restrict__ sval, int* __restrict__ ccp, int* __restrict__ irow_t, V* __restrict__ val_t,
-            WccsInfo* __restrict__ info) {
-    constexpr int kCap = kPlStageBytes / (4 + (int)sizeof(V));
-    __shared__ int cnt[kPlWaves * kBcCols];
-    __shared__ int colptr[kBcCols + 1];
-    __shared__ int s_row[kCap];
-    __shared__ V s_val[kCap];
-    const int b = (int)xcd_block(blockIdx.x, gridDim.x);
-    const int s = bstart[b], e = bstart[b + 1], m = e - s;
+struct PlaceSmem {
+    static constexpr int kCap = kPlStageBytes / (4 + (int)sizeof(V));
+    int cnt[kPlWaves * kBcCols];
+    int colptr[kBcCols + 1];
+    int s_row[kCap];
+    V s_val[kCap];
+};
+
+// Column lengths of block b from the per-wave counts, the column pointer,
+// the longest column and each wave's start inside every column, in wave
+// order (the first wave; lane j owns column j).  Between two barriers.
+template <typename V>
+__device__ __forceinline__ void place_columns(PlaceSmem<V>& sm, int n, int nb, int b, int s, int e, int* ccp,
+                                              WccsInfo* info) {
+    const int lane = threadIdx.x & (kWave - 1);
+    if (threadIdx.x >= kWave) return;
     const int c0 = b * kBcCols, ncols = min(kBcCols, n - c0);
+    int tot = 0;
+    for (int ww = 0; ww < kPlWaves; ++ww) tot += sm.cnt[ww * kBcCols + lane];
+    int incl = tot;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int u = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += u;
+    }
+    int run = incl - tot;
+    sm.colptr[lane] = run;
+    if (lane < ncols) ccp[c0 + lane] = s + run;
+    if (b == nb - 1 && lane == 0) ccp[n] = e;
+    for (int ww = 0; ww < kPlWaves; ++ww) {
+        const int c = sm.cnt[ww * kBcCols + lane];
+        sm.cnt[ww * kBcCols + lane] = run;
+        run += c;
+    }
+    int mx = tot;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, kWave));
+    // every block would otherwise hit the one counter with an atomic; most
+    // blocks see it already at their maximum
+    if (lane == 0 && mx > __hip_atomic_load(&info->kmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(&info->kmax, mx);
+}
+
+// Stable placement of one group of 64 consecutive entries of a wave's
+// stretch (p < we valid): rank among the group's entries of the same column
+// by ballots, slot from the wave's cursor of that column.
+template <typename V>
+__device__ __forceinline__ void place_group(PlaceSmem<V>& sm, int* mine, int p, int we, uint32_t k, V v, bool staged,
+                                            int s, int* irow_t, V* val_t) {
+    const bool valid = p < we;
+    const uint32_t lc = k & (kBcCols - 1);
+    const uint64_t mm = match_low_bits(lc, kBcBits, __ballot(valid));
+    const int rank = (int)__popcll(mm & lanes_below());
+    int slot = 0;
+    if (valid) slot = mine[lc];
+    if (valid && rank == 0) mine[lc] = slot + (int)__popcll(mm);
+    if (valid) {
+        const int q = slot + rank;
+        if (staged) { sm.s_row[q] = (int)(k >> kBcBits); sm.s_val[q] = v; }
+        else { irow_t[s + q] = (int)(k >> kBcBits); val_t[s + q] = v; }
+    }
+}
+
+// Block b on its own: entries read once to count and again to place.
+template <typename V>
+__device__ void place_block(PlaceSmem<V>& sm, int n, int nb, int b, const int* bstart, const uint32_t* key,
+                            const V* sval, int* ccp, int* irow_t, V* val_t, WccsInfo* info) {
+    const int s = bstart[b], e = bstart[b + 1], m = e - s;
     const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-    for (int i = threadIdx.x; i < kPlWaves * kBcCols; i += kPlThreads) cnt[i] = 0;
+    __syncthreads();   // the previous block's stage is written out
+    for (int i = threadIdx.x; i < kPlWaves * kBcCols; i += kPlThreads) sm.cnt[i] = 0;
     __syncthreads();
     int ws, we;
     stretch(s, e, kPlWaves, w, ws, we);
-    int* mine = cnt + w * kBcCols;
+    int* mine = sm.cnt + w * kBcCols;
     for (int p = ws + lane; p < we; p += kWave) atomicAdd(&mine[key[p] & (kBcCols - 1)], 1);
     __syncthreads();
-    // column lengths, their exclusive prefix (the column pointer), the longest
-    // (the first wave; each lane owns kBcCols / 64 consecutive columns)
-    if (threadIdx.x < kWave) {
-        constexpr int kPer = kBcCols / kWave;
-        static_assert(kPer >= 1 && kBcCols % kWave == 0, "columns per block: a multiple of the wave");
-        int tot[kPer];
-        int sum = 0, mx = 0;
-#pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            const int j = lane * kPer + q;
-            int t0 = 0;
-            for (int ww = 0; ww < kPlWaves; ++ww) t0 += cnt[ww * kBcCols + j];
-            tot[q] = t0;
-            sum += t0;
-            mx = max(mx, t0);
-        }
-        int incl = sum;
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            const int u = __shfl_up(incl, off, kWave);
-            if (lane >= off) incl += u;
-        }
-        int run = incl - sum;
-#pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            colptr[lane * kPer + q] = run;
-            run += tot[q];
-        }
-        if (lane == kWave - 1) colptr[kBcCols] = incl;
-#pragma unroll
-        for (int off = kWave / 2; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, kWave));
-        if (lane == 0 && mx > 0) atomicMax(&info->kmax, mx);
-    }
+    place_columns(sm, n, nb, b, s, e, ccp, info);
     __syncthreads();
-    for (int j = threadIdx.x; j < ncols; j += kPlThreads) ccp[c0 + j] = s + colptr[j];
-    if (b == nb - 1 && threadIdx.x == 0) ccp[n] = e;
-    // each wave's start inside every column, in wave order
-    for (int j = threadIdx.x; j < kBcCols; j += kPlThreads) {
-        int run = colptr[j];
-        for (int ww = 0; ww < kPlWaves; ++ww) {
-            const int c = cnt[ww * kBcCols + j];
-            cnt[ww * kBcCols + j] = run;
-            run += c;
-        }
-    }
-    __syncthreads();
-    const bool staged = m <= kCap;
-    const uint64_t below = lanes_below();
+    const bool staged = m <= PlaceSmem<V>::kCap;
     for (int base = ws; base < we; base += kWave) {
         const int p = base + lane;
-        const bool valid = p < we;
         uint32_t k = 0;
         V v = 0;
-        if (valid) { k = key[p]; v = sval[p]; }
-        const uint32_t lc = k & (kBcCols - 1);
-        const uint64_t mm = match_low_bits(lc, kBcBits, __ballot(valid));
-        const int rank = (int)__popcll(mm & below);
-        int slot = 0;
-        if (valid) slot = mine[lc];
-        if (valid && rank == 0) mine[lc] = slot + (int)__popcll(mm);
-        if (valid) {
-            const int q = slot + rank;
-            if (staged) { s_row[q] = (int)(k >> kBcBits); s_val[q] = v; }
-            else { irow_t[s + q] = (int)(k >> kBcBits); val_t[s + q] = v; }
-        }
+        if (p < we) { k = key[p]; v = sval[p]; }
+        place_group(sm, mine, p, we, k, v, staged, s, irow_t, val_t);
     }
     if (!staged) return;
     __syncthreads();
     for (int q = threadIdx.x; q < m; q += kPlThreads) {
-        irow_t[s + q] = s_row[q];
-        val_t[s + q] = s_val[q];
+        irow_t[s + q] = sm.s_row[q];
+        val_t[s + q] = sm.s_val[q];
+    }
+}
+
+// One workgroup per kPlBlocks consecutive blocks.  When every block of the
+// group fits the stage and its wave stretches fit kPlPer groups of 64, all
+// of the group's entries are loaded into registers at once, so one round
+// trip to memory serves several blocks; each block is then counted,
+// numbered, placed in LDS and written out in turn.  Otherwise the blocks
+// are placed one by one, reading their entries twice.
+template <typename V>
+__global__ void __launch_bounds__(kPlThreads)
+k_bcs_place(int n, int nb, const int* __restrict__ bstart, const uint32_t* __restrict__ key,
+            const V* __restrict__ sval, int* __restrict__ ccp, int* __restrict__ irow_t, V* __restrict__ val_t,
+            WccsInfo* __restrict__ info) {
+    __shared__ PlaceSmem<V> sm;
+    const int b0 = (int)xcd_block(blockIdx.x, gridDim.x) * kPlBlocks;
+    const int nblk = min(kPlBlocks, nb - b0);
+    const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    bool held = true;
+    for (int i = 0; i < nblk; ++i) {
+        const int m = bstart[b0 + i + 1] - bstart[b0 + i];
+        held = held && m <= PlaceSmem<V>::kCap && (m + kPlWaves - 1) / kPlWaves <= kPlPer * kWave;
+    }
+    if (!held) {
+        for (int i = 0; i < nblk; ++i) place_block(sm, n, nb, b0 + i, bstart, key, sval, ccp, irow_t, val_t, info);
+        return;
+    }
+    uint32_t kk[kPlBlocks][kPlPer];
+    V vv[kPlBlocks][kPlPer];
+#pragma unroll
+    for (int i = 0; i < kPlBlocks; ++i) {
+        int ws = 0, we = 0;
+        if (i < nblk) stretch(bstart[b0 + i], bstart[b0 + i + 1], kPlWaves, w, ws, we);
+#pragma unroll
+        for (int u = 0; u < kPlPer; ++u) {
+            const int p = ws + u * kWave + lane;
+            kk[i][u] = 0;
+            vv[i][u] = 0;
+            if (p < we) { kk[i][u] = key[p]; vv[i][u] = sval[p]; }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kPlBlocks; ++i) {
+        if (i >= nblk) break;
+        const int b = b0 + i;
+        const int s = bstart[b], e = bstart[b + 1], m = e - s;
+        int ws, we;
+        stretch(s, e, kPlWaves, w, ws, we);
+        int* mine = sm.cnt + w * kBcCols;
+        __syncthreads();   // the previous block's stage is written out
+        for (int t = threadIdx.x; t < kPlWaves * kBcCols; t += kPlThreads) sm.cnt[t] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kPlPer; ++u)
+            if (ws + u * kWave + lane < we) atomicAdd(&mine[kk[i][u] & (kBcCols - 1)], 1);
+        __syncthreads();
+        place_columns(sm, n, nb, b, s, e, ccp, info);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kPlPer; ++u)
+            if (ws + u * kWave < we) place_group(sm, mine, ws + u * kWave + lane, we, kk[i][u], vv[i][u], true, s, irow_t,
+                                                 val_t);
+        __syncthreads();
+        for (int q = threadIdx.x; q < m; q += kPlThreads) {
+            irow_t[s + q] = sm.s_row[q];
+            val_t[s + q] = sm.s_val[q];
+        }
     }
 }
 
@@ -329,8 +399,8 @@ static hipError_t wccs_back_t(const WccsGeom& g, int n, int bw, const int* irp, 
     hipLaunchKernelGGL(k_bcs_distribute<V>, dim3((unsigned)g.tiles), dim3(kBcThreads), lds, s, n, bw, g.nwbmax,
                        g.wb_bits, irp, icol, (const V*)val, table, bstart, key, (V*)sval);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bcs_place<V>, dim3((unsigned)g.nb), dim3(kPlThreads), 0, s, n, g.nb, bstart, key,
-                       (const V*)sval, ccp, irow_t, (V*)val_t, info);
+    hipLaunchKernelGGL(k_bcs_place<V>, dim3((unsigned)((g.nb + kPlBlocks - 1) / kPlBlocks)), dim3(kPlThreads), 0, s,
+                       n, g.nb, bstart, key, (const V*)sval, ccp, irow_t, (V*)val_t, info);
     return hipGetLastError();
 }
 
