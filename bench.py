@@ -499,6 +499,7 @@ def main():
         "at_decision": decision,
         "precision": h["precision"],
         "kernel_source_sha": kernel_source_sha(),
+        "table_kernel_sha": table_kernel_sha(),
     }
     x64 = h.pop("x64")
     if not args.no_extra and args.workload == "stencil27_128":
@@ -552,7 +553,8 @@ def model_decision(path, h):
 
 def table_matches_kernels(path):
     """Whether the auto-tuning table was measured with the kernels built here
-    (its kernel_source_sha equals this tree's), or None without a stamp."""
+    (its kernel_source_sha equals the hash of this tree's sources of the
+    kernels the off-line phase times), or None without a stamp."""
     if not path or not os.path.exists(path):
         return None
     import paper_2407_00019_amd as spmvat
@@ -589,6 +591,11 @@ def cpu_model():
 
 def kernel_source_sha():
     from paper_2407_00019_amd import kernel_source_sha as sha
+    return sha()
+
+
+def table_kernel_sha():
+    from paper_2407_00019_amd import table_kernel_sha as sha
     return sha()
 
 

@@ -481,25 +481,39 @@ def at_table_from_json(d: dict) -> at_table:
     return t
 
 
-def kernel_source_sha() -> str:
-    """Hash of the kernel sources (csrc/*.hip, *.h, less the header of the
-    host-only code): a table or profile measured with other kernels carries
-    another value."""
+# Sources of the kernels the off-line phase times (row statistics, the COO
+# and ELL transformations, the CRS / COO-Row / ELL-Row SpMVs and the serving
+# step it calibrates the margin on): the auto-tuning table depends on these
+# only.
+TABLE_KERNEL_SOURCES = ("common.h", "spmv_rows.h", "k_stats.hip", "k_transform.hip", "k_spmv.hip", "k_serve.hip")
+
+
+def kernel_source_sha(files=None) -> str:
+    """Hash of kernel sources: by default every csrc/*.hip and *.h but the
+    header of the host-only code; else the named files of csrc.  A table or
+    profile measured with other kernels carries another value."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(_HERE, "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")) and f != "host_core.h":
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+    names = sorted(files) if files is not None else \
+        [f for f in sorted(os.listdir(d)) if f.endswith((".hip", ".h")) and f != "host_core.h"]
+    for f in names:
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
+def table_kernel_sha() -> str:
+    """Hash of the sources of the kernels the off-line table is measured on."""
+    return kernel_source_sha(TABLE_KERNEL_SOURCES)
+
+
 def table_matches_kernels(d: dict):
-    """Whether an off-line table (its JSON) was measured with the kernels of
-    this tree: True / False, or None when the table carries no stamp."""
+    """Whether an off-line table (its JSON) was measured with this tree's
+    kernels of the off-line phase: True / False, or None when the table
+    carries no stamp."""
     sha = d.get("kernel_source_sha")
-    return None if sha is None else sha == kernel_source_sha()
+    return None if sha is None else sha == table_kernel_sha()
 
 
 def convert_values(val64: torch.Tensor, to: int, stream=None) -> torch.Tensor:

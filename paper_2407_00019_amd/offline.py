@@ -340,7 +340,7 @@ def main(argv=None):
     f64 = [p["f64"] for p in points if "f64" in p]
     fams = [p["family"] for p in points if "f64" in p]
     table = {"c": a.c, "machine": torch.cuda.get_device_name(0), "points": len(f64),
-             "kernel_source_sha": spmvat.kernel_source_sha()}
+             "kernel_source_sha": spmvat.table_kernel_sha()}
     for base in ("scalar", "best"):
         for fam in sorted(set(fams)) + ["all"]:
             sel = [q for q, f in zip(f64, fams) if fam == "all" or f == fam]

@@ -203,14 +203,18 @@ def test_table_margin_replaces_the_default():
 
 def test_off_line_table_is_stamped_with_the_kernel_sources():
     """The committed auto-tuning table names the kernel sources it was
-    measured with (a hash of csrc/*.hip and *.h), carries a measured
-    margin, and the library's JSON reader takes the margin over."""
+    measured with (a hash of the sources of the kernels the off-line phase
+    times), carries a measured margin, and the library's JSON reader takes
+    the margin over."""
     import json
     spmvat = _lib()
     with open(os.path.join(ROOT, "paper_2407_00019_amd", "at_table.json")) as f:
         d = json.load(f)
     assert isinstance(d.get("kernel_source_sha"), str) and len(d["kernel_source_sha"]) == 16
     assert spmvat.table_matches_kernels(d) in (True, False)
+    # the stamp covers exactly those sources: another file's change leaves it
+    assert spmvat.table_kernel_sha() == spmvat.kernel_source_sha(spmvat.TABLE_KERNEL_SOURCES)
+    assert spmvat.table_kernel_sha() != spmvat.kernel_source_sha()
     assert d["k_margin"] >= 1.0
     assert spmvat.at_table_from_json(d).k_margin == pytest.approx(d["k_margin"])
 
