@@ -417,6 +417,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-oracle SpMV sample")
     ap.add_argument("--spmv-reps", type=int, default=3,
                     help="back-to-back SpMVs per format in each step (one event pair around them)")
+    ap.add_argument("--serve-repeats", type=int, default=5,
+                    help="replays of the serving stream per policy and arrival mode (alternating policies)")
     ap.add_argument("--serve-jobs", type=int, default=2048,
                     help="jobs of the serving stream replayed after the timed steps (0: skip)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -525,7 +527,7 @@ def main():
             torch.cuda.empty_cache()
         out["workloads"] = extra
     if args.serve_jobs > 0:
-        out["serving"] = serving(args.serve_jobs)
+        out["serving"] = serving(args.serve_jobs, args.serve_repeats)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(m, x64, args.cpu_seconds, with_ell=h["ell_row"])
     print(json.dumps(out), flush=True)
@@ -562,7 +564,7 @@ def table_matches_kernels(path):
         return spmvat.table_matches_kernels(json.load(f))
 
 
-def serving(count):
+def serving(count, repeats=5):
     """The serving stream (first `count` jobs), replayed through the
     continuous-batching server, auto-tuned vs always-CRS (binary32)."""
     import gen
@@ -571,7 +573,7 @@ def serving(count):
     jobs = serve.build_jobs(gen.serving_jobs(count, rate_per_s=0.0))
     log(f"[bench] serving: built {count} jobs ({sum(j.nnz for j in jobs) / 1e6:.0f}M nonzeros) "
         f"in {time.time() - t0:.1f}s")
-    res = serve.compare(jobs, slots=serve.DEFAULT_SLOTS, hbm_cap=200 << 30, rate="auto", log=log)
+    res = serve.compare(jobs, slots=serve.DEFAULT_SLOTS, hbm_cap=200 << 30, rate="auto", log=log, repeats=repeats)
     res["jobs_of_stream"] = count
     res["nnz_total"] = int(sum(j.nnz for j in jobs))
     return res
