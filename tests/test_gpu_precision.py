@@ -26,6 +26,8 @@ MATS = [
     ("rand_n4002", lambda: gen.random_small(4002, 13, 40, False, False, 0.1, integer_values=False)),
     # the D_mat-sweep shape at full size (n = 1,048,576, 32 per row, D_mat = 0)
     ("dsweep_local_d0", lambda: gen.dsweep_matrix(0, local=True)),
+    # bandwidth ~ n = 100,000: the column kernels' row windows exceed the LDS page table
+    ("wide_sparse", lambda: gen.random_small(100000, 7, 3, True, False, 0.1, integer_values=False)),
 ]
 DTYPES = [(1, "f32"), (2, "bf16"), (3, "f16")]
 
