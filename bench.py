@@ -223,7 +223,8 @@ class PathRunner:
         import torch
         sp = self.sp
         out = {}
-        for name, alg in (("sort", sp.CCS_SORT), ("bucketed", sp.CCS_BUCKETED), ("banded", sp.CCS_BANDED)):
+        for name, alg in (("sort", sp.CCS_SORT), ("bucketed", sp.CCS_BUCKETED), ("banded", sp.CCS_BANDED),
+                          ("radix", sp.CCS_RADIX)):
             plan = sp.spmv_plan_create(self.n, self.nnz, self.irp, self.icol, self.val, self.dtype, self.work)
             try:
                 sp.spmv_plan_set_ccs_algorithm(plan, alg)

@@ -172,21 +172,26 @@ spmv_status spmv_plan_set_limit(spmv_plan *p, size_t max_format_bytes);
 
 /* Algorithms of the CRS -> CCS transformation (Phase I of section 2.1).
  * All give the same arrays bit for bit; they differ in speed by structure.
- *   AUTO      chosen from the bandwidth and n (the default)
+ *   AUTO      BANDED when it applies, else RADIX (the default)
  *   SORT      column counts, a scatter of (position, row) keys through
  *             per-column cursors, then a per-column sort of the keys
  *   BUCKETED  two-level stable counting sort over all 1024-column blocks
  *             (n <= 2^22)
- *   BANDED    two-level stable counting sort over the 128-column blocks of
- *             each row tile's column window (limited bandwidth) */
+ *   BANDED    two-level stable counting sort over the 64-column blocks of
+ *             each row tile's column window (limited bandwidth)
+ *   RADIX     least-significant-digit radix sort of the entries by column,
+ *             8 bits per pass, each pass a stable counting sort over 4096-
+ *             entry tiles (any n; the workspace holds two copies of the
+ *             entries) */
 typedef enum {
-    SPMV_CCS_AUTO = 0, SPMV_CCS_SORT = 1, SPMV_CCS_BUCKETED = 2, SPMV_CCS_BANDED = 3
+    SPMV_CCS_AUTO = 0, SPMV_CCS_SORT = 1, SPMV_CCS_BUCKETED = 2, SPMV_CCS_BANDED = 3,
+    SPMV_CCS_RADIX = 4
 } spmv_ccs_algorithm;
 
 /* Host only.  Selects the algorithm csr_to_ccs (and spmv_buffer_sizes for
  * CCS) uses from now on.  SPMV_E_ARG for an unknown value or one that does
  * not apply to the matrix (BUCKETED with n > 2^22; BANDED when a row
- * tile's column window is too wide or n > 2^25). */
+ * tile's column window is too wide or n > 2^26). */
 spmv_status spmv_plan_set_ccs_algorithm(spmv_plan *p, spmv_ccs_algorithm alg);
 
 /* Host only.  Output and workspace sizes of the transformation into `f`

@@ -25,7 +25,7 @@ _LIB = None
 # enums of spmvat.h
 SPMV_OK, SPMV_E_ARG, SPMV_E_MATRIX, SPMV_E_TOO_LARGE, SPMV_E_NOT_READY, SPMV_E_HIP = range(6)
 CRS, COO_ROW, CCS, COO_COL, ELL_ROW, ELL_COL = range(6)
-CCS_AUTO, CCS_SORT, CCS_BUCKETED, CCS_BANDED = range(4)   # spmv_ccs_algorithm
+CCS_AUTO, CCS_SORT, CCS_BUCKETED, CCS_BANDED, CCS_RADIX = range(5)   # spmv_ccs_algorithm
 F64, F32, BF16, F16 = range(4)
 FORMAT_NAMES = {CRS: "crs", COO_ROW: "coo_row", CCS: "ccs", COO_COL: "coo_col", ELL_ROW: "ell_row",
                 ELL_COL: "ell_col"}

@@ -55,20 +55,17 @@ size_t crs_bytes(const spmv_plan* p) {
 }
 
 // CRS -> CCS algorithm (spmv_ccs_algorithm).  Chosen by the matrix's
-// structure unless the plan names one:
-//  - limited bandwidth (a row tile's window of 128-column blocks fits the
-//    kernels' LDS): the banded two-level counting sort;
-//  - else scattered columns with n <= 2^22: the two-level counting sort
-//    over all column blocks;
-//  - else column counts, a scatter of keys and per-column sorts.
+// structure unless the plan names one: limited bandwidth (a row tile's
+// window of 64-column blocks fits the kernels' LDS) takes the banded
+// two-level counting sort, everything else the radix sort by column.  The
+// sort and bucketed routes stay selectable.
 bool ccs_banded_ok(int32_t n, int32_t bw, int32_t max_row) { return wccs_geom(n, bw, max_row).usable; }
 bool ccs_bucketed_ok(int32_t n) { return n <= (1 << kCcsRowBits); }
 
 int ccs_route(int32_t n, int32_t bw, int32_t max_row, int alg) {
     if (alg != SPMV_CCS_AUTO) return alg;
     if (ccs_banded_ok(n, bw, max_row)) return SPMV_CCS_BANDED;
-    if (ccs_bucketed_ok(n) && !ccs_privatised(bw)) return SPMV_CCS_BUCKETED;
-    return SPMV_CCS_SORT;
+    return SPMV_CCS_RADIX;
 }
 
 // CCS workspace layout: bucketed -- count table, its chunk sums, summary,
@@ -80,12 +77,29 @@ struct CcsWs {
     size_t cursor, bsum, mid, lng, ext, sum, info, keys, tmp;   // sort and windowed routes
     size_t wtable, bstart, wkey, wval;                        // windowed route (overlays keys)
     size_t table, csum, bkey, bval;                           // bucketed route
+    size_t xcol, xrow, xval, ycol, yrow, yval;                // radix route (with table, csum, sum)
     size_t total;
 };
 CcsWs ccs_ws(int32_t n, int64_t nnz, int vb, int32_t bw, int32_t max_row, int alg) {
     CcsWs w{};
     size_t o = 0;
     const int route = ccs_route(n, bw, max_row, alg);
+    if (route == SPMV_CCS_RADIX) {
+        const RadixGeom g = radix_geom(n, nnz);
+        const size_t e4 = round_up((size_t)std::max<int64_t>(nnz, 1) * 4, kAlign);
+        const size_t ev = round_up((size_t)std::max<int64_t>(nnz, 1) * vb, kAlign);
+        w.xcol = o; o += e4;
+        w.xrow = o; o += e4;
+        w.xval = o; o += ev;
+        w.ycol = o; o += e4;
+        w.yrow = o; o += e4;
+        w.yval = o; o += ev;
+        w.table = o; o += round_up((size_t)std::max<int64_t>(g.table, 1) * 4, kAlign);
+        w.csum = o;  o += round_up((size_t)std::max<int64_t>(g.chunks, 1) * 4, kAlign);
+        w.sum = o;   o += round_up(sizeof(ColSummary), kAlign);
+        w.total = o;
+        return w;
+    }
     if (route == SPMV_CCS_BUCKETED) {
         const CcsGeom g = ccs_geom(n);
         w.table = o; o += round_up((size_t)g.table * 4, kAlign);
@@ -249,6 +263,7 @@ SPMV_API spmv_status spmv_plan_set_ccs_algorithm(spmv_plan* p, spmv_ccs_algorith
     switch (alg) {
         case SPMV_CCS_AUTO:
         case SPMV_CCS_SORT:
+        case SPMV_CCS_RADIX:
             break;
         case SPMV_CCS_BUCKETED:
             if (!ccs_bucketed_ok(p->n)) return SPMV_E_ARG;
@@ -365,6 +380,30 @@ SPMV_API spmv_status csr_to_ccs(spmv_plan* p, const spmv_buffers* out, void* wor
         return SPMV_OK;
     };
 
+    if (route == SPMV_CCS_RADIX) {
+        // passes of a stable counting sort by 8-bit column digits, least
+        // significant first; the column pointer from the sorted columns; one
+        // sync at the end for the longest column
+        const RadixGeom g = radix_geom(p->n, p->nnz);
+        RadixWs rw{};
+        rw.xcol = reinterpret_cast<int32_t*>(base + w.xcol);
+        rw.xrow = reinterpret_cast<int32_t*>(base + w.xrow);
+        rw.xval = base + w.xval;
+        rw.ycol = reinterpret_cast<int32_t*>(base + w.ycol);
+        rw.yrow = reinterpret_cast<int32_t*>(base + w.yrow);
+        rw.yval = base + w.yval;
+        rw.table = reinterpret_cast<int32_t*>(base + w.table);
+        rw.csum = reinterpret_cast<int32_t*>(base + w.csum);
+        if (p->nnz == 0) HIP_TRY(p, launch_fill_zero(ccp, ((int64_t)p->n + 1) * 4, s));
+        HIP_TRY(p, launch_ccs_radix(g, p->n, p->nnz, p->irp, p->icol, p->val, vb, rw, ccp, irow_t, val_t, dsum, s));
+        HIP_TRY(p, hipMemcpyAsync(&cs, dsum, sizeof(cs), hipMemcpyDeviceToHost, s));
+        HIP_TRY(p, hipStreamSynchronize(s));
+        if ((int64_t)cs.total != p->nnz) {
+            p->err = "column pointer does not end at nnz";
+            return SPMV_E_HIP;
+        }
+        return built();
+    }
     if (route == SPMV_CCS_BUCKETED) {
         // level 1 (count table, its scan, ordered distribution to column
         // blocks) and level 2 (ordered placement inside each block); one sync

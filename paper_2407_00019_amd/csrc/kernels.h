@@ -81,6 +81,26 @@ CcsGeom ccs_geom(int n);
 hipError_t launch_ccs_bucketed(const CcsGeom& g, int n, int64_t nnz, const int* irp, const int* icol,
                                const void* val, int vbytes, int* table, int* csum, uint32_t* bkey, void* bval,
                                int* ccp, int* irow_t, void* val_t, ColSummary* sum, hipStream_t s);
+// Radix CRS -> CCS: a least-significant-digit sort of the entries by column,
+// 8 bits per pass, for matrices whose columns are scattered.  Buffers of
+// the workspace: two sets of (column, row, value) arrays of nnz entries,
+// the (digit, tile) count table and its scan's chunk sums.
+struct RadixGeom {
+    int passes;          // 8-bit digits of the largest column index
+    int64_t tiles;       // 4096-entry tiles
+    int64_t table;       // 256 x tiles counts
+    int64_t chunks;      // 4096-count chunks of the table scan
+};
+RadixGeom radix_geom(int n, int64_t nnz);
+struct RadixWs {
+    int *xcol, *xrow, *ycol, *yrow;
+    void *xval, *yval;
+    int* table;
+    int* csum;
+};
+hipError_t launch_ccs_radix(const RadixGeom& g, int n, int64_t nnz, const int* irp, const int* icol,
+                            const void* val, int vbytes, const RadixWs& ws, int* ccp, int* irow_t, void* val_t,
+                            ColSummary* sum, hipStream_t s);
 // Banded CRS -> CCS for matrices of limited bandwidth (a two-level stable
 // counting sort with coalesced stores): per-(tile, wave) counts over the
 // 128-column blocks of each row tile's column window, a per-block walk over

@@ -625,7 +625,7 @@ CCS_CASES = {
 }
 
 
-@pytest.mark.parametrize("alg", ["sort", "bucketed", "banded"])
+@pytest.mark.parametrize("alg", ["sort", "bucketed", "banded", "radix"])
 @pytest.mark.parametrize("case", sorted(CCS_CASES))
 def test_ccs_every_algorithm(case, alg):
     """Each CRS -> CCS algorithm, selected on the plan, on matrices of every
@@ -639,7 +639,8 @@ def test_ccs_every_algorithm(case, alg):
     assert oracle.validate_crs(m.n, m.irp, m.icol) == 0
     irp, icol, val = to_dev(m)
     plan = spmvat.Plan(irp, icol, val)
-    code = {"sort": spmvat.CCS_SORT, "bucketed": spmvat.CCS_BUCKETED, "banded": spmvat.CCS_BANDED}[alg]
+    code = {"sort": spmvat.CCS_SORT, "bucketed": spmvat.CCS_BUCKETED, "banded": spmvat.CCS_BANDED,
+            "radix": spmvat.CCS_RADIX}[alg]
     ccp, irow_t, val_t = plan.to_ccs(algorithm=code)
     (jcol,) = plan.to_coo(column_wise=True)
     o_ccp, o_irow_t, o_val_t = oracle.csr_to_ccs(m.n, m.irp, m.icol, m.val)
@@ -652,6 +653,45 @@ def test_ccs_every_algorithm(case, alg):
     yref = oracle.spmv_crs(m.n, m.irp, m.icol, m.val, x)
     y = host(plan.spmv(spmvat.COO_COL, torch.from_numpy(x).to("cuda:0")))
     assert oracle.rel_l2(y, yref) <= TOL64
+    plan.close()
+
+
+def one_per_row(n, seed):
+    """One entry per row at a random column: nnz = n exactly."""
+    rng = np.random.default_rng(seed)
+    irp = np.arange(n + 1, dtype=np.int32)
+    icol = rng.integers(0, n, size=n).astype(np.int32)
+    return gen.Crs(n, irp, icol, rng.standard_normal(n), f"one_per_row_{n}")
+
+
+RADIX_CASES = {
+    # one, two and three 8-bit passes, and the edges of a tile of 4096 entries
+    "n200_one_pass": lambda: gen.random_small(200, 31, 9, False, True, 0.1, integer_values=False),
+    "n257_two_passes": lambda: gen.random_small(257, 32, 30, True, False, 0.2, integer_values=False),
+    "n70000_three_passes": lambda: gen.random_small(70000, 33, 12, False, False, 0.1, integer_values=False),
+    "nnz_4096": lambda: one_per_row(4096, 34),
+    "nnz_4097": lambda: one_per_row(4097, 35),
+    "no_entries": lambda: gen.random_small(300, 6, 0, True, False, 0.0, integer_values=False),
+    "single_row": lambda: gen.random_small(1, 5, 1, True, False, 0.0, integer_values=False),
+}
+
+
+@pytest.mark.parametrize("case", sorted(RADIX_CASES))
+def test_ccs_radix_passes(case):
+    """The radix CRS -> CCS with one, two and three digit passes, tiles cut
+    at and across 4096 entries, no entries, one row: CCS bit-exact with the
+    oracle and the longest column right."""
+    spmvat = lib_ready()
+    m = RADIX_CASES[case]()
+    assert oracle.validate_crs(m.n, m.irp, m.icol) == 0
+    irp, icol, val = to_dev(m)
+    plan = spmvat.Plan(irp, icol, val)
+    ccp, irow_t, val_t = plan.to_ccs(algorithm=spmvat.CCS_RADIX)
+    o_ccp, o_irow_t, o_val_t = oracle.csr_to_ccs(m.n, m.irp, m.icol, m.val)
+    assert np.array_equal(host(ccp), o_ccp)
+    assert np.array_equal(host(irow_t), o_irow_t)
+    assert np.array_equal(bits(host(val_t)), bits(o_val_t))
+    assert plan.stats.max_col == (int(np.diff(o_ccp).max()) if m.n else 0)
     plan.close()
 
 
