@@ -180,7 +180,7 @@ spmv_status spmv_plan_set_limit(spmv_plan *p, size_t max_format_bytes);
  *   BANDED    two-level stable counting sort over the 64-column blocks of
  *             each row tile's column window (limited bandwidth)
  *   RADIX     least-significant-digit radix sort of the entries by column,
- *             8 bits per pass, each pass a stable counting sort over 4096-
+ *             8 bits per pass, each pass a stable counting sort over 2048-
  *             entry tiles (any n; the workspace holds two copies of the
  *             entries) */
 typedef enum {

@@ -87,7 +87,7 @@ hipError_t launch_ccs_bucketed(const CcsGeom& g, int n, int64_t nnz, const int* 
 // the (digit, tile) count table and its scan's chunk sums.
 struct RadixGeom {
     int passes;          // 8-bit digits of the largest column index
-    int64_t tiles;       // 4096-entry tiles
+    int64_t tiles;       // 2048-entry tiles
     int64_t table;       // 256 x tiles counts
     int64_t chunks;      // 4096-count chunks of the table scan
 };

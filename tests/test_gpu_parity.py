@@ -665,12 +665,13 @@ def one_per_row(n, seed):
 
 
 RADIX_CASES = {
-    # one, two and three 8-bit passes, and the edges of a tile of 4096 entries
+    # one, two and three 8-bit passes, and the edges of tiles of 2048 entries
     "n200_one_pass": lambda: gen.random_small(200, 31, 9, False, True, 0.1, integer_values=False),
     "n257_two_passes": lambda: gen.random_small(257, 32, 30, True, False, 0.2, integer_values=False),
     "n70000_three_passes": lambda: gen.random_small(70000, 33, 12, False, False, 0.1, integer_values=False),
-    "nnz_4096": lambda: one_per_row(4096, 34),
-    "nnz_4097": lambda: one_per_row(4097, 35),
+    "nnz_2048": lambda: one_per_row(2048, 34),
+    "nnz_2049": lambda: one_per_row(2049, 35),
+    "nnz_4097": lambda: one_per_row(4097, 36),
     "no_entries": lambda: gen.random_small(300, 6, 0, True, False, 0.0, integer_values=False),
     "single_row": lambda: gen.random_small(1, 5, 1, True, False, 0.0, integer_values=False),
 }
@@ -679,7 +680,7 @@ RADIX_CASES = {
 @pytest.mark.parametrize("case", sorted(RADIX_CASES))
 def test_ccs_radix_passes(case):
     """The radix CRS -> CCS with one, two and three digit passes, tiles cut
-    at and across 4096 entries, no entries, one row: CCS bit-exact with the
+    at and across 2048 entries, no entries, one row: CCS bit-exact with the
     oracle and the longest column right."""
     spmvat = lib_ready()
     m = RADIX_CASES[case]()
