@@ -34,6 +34,8 @@ constexpr int kRxPer = 8;                             // entries per thread
 constexpr int kRxTile = kRxThreads * kRxPer;          // entries per tile
 constexpr int kRxGroups = kRxTile / kRxWaves / kWave; // groups of 64 per wave
 constexpr int kRxScan = 4096;                         // table entries per scan workgroup
+constexpr int kRxHistTiles = 4;                       // tiles per histogram workgroup
+constexpr int kRxCcpPer = 8;                          // sorted columns per thread (column pointer)
 static_assert(kRxThreads == kRxBins, "one thread per digit value in the tile scan");
 static_assert(kRxScan % kRxThreads == 0, "the scan gives each thread whole runs");
 
@@ -73,20 +75,36 @@ RadixGeom radix_geom(int n, int64_t nnz) {
 
 // ------------------------------------------------------------------ hist
 
+// kRxHistTiles tiles per workgroup; each thread counts 8 consecutive
+// entries of a tile (two 16-byte loads).
 __global__ void __launch_bounds__(kRxThreads)
 k_rx_hist(int64_t nnz, int64_t tiles, int shift, const int* __restrict__ col, int* __restrict__ table) {
-    __shared__ int h[kRxBins];
-    const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t t0 = tile * kRxTile;
-    h[threadIdx.x] = 0;
+    static_assert(kRxPer == 8, "two 16-byte loads per thread and tile");
+    __shared__ int h[kRxHistTiles * kRxBins];
+    const int64_t tb = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kRxHistTiles;
+    for (int i = threadIdx.x; i < kRxHistTiles * kRxBins; i += kRxThreads) h[i] = 0;
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kRxPer; ++j) {
-        const int64_t q = t0 + j * kRxThreads + threadIdx.x;
-        if (q < nnz) atomicAdd(&h[(col[q] >> shift) & (kRxBins - 1)], 1);
+    for (int tt = 0; tt < kRxHistTiles; ++tt) {
+        const int64_t q0 = (tb + tt) * kRxTile + (int64_t)threadIdx.x * kRxPer;
+        if (tb + tt >= tiles || q0 >= nnz) continue;
+        int c[kRxPer];
+        if (q0 + kRxPer <= nnz) {
+            const int4 a = *reinterpret_cast<const int4*>(col + q0);
+            const int4 b = *reinterpret_cast<const int4*>(col + q0 + 4);
+            c[0] = a.x; c[1] = a.y; c[2] = a.z; c[3] = a.w; c[4] = b.x; c[5] = b.y; c[6] = b.z; c[7] = b.w;
+        } else {
+#pragma unroll
+            for (int k = 0; k < kRxPer; ++k) c[k] = q0 + k < nnz ? col[q0 + k] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < kRxPer; ++k)
+            if (c[k] >= 0) atomicAdd(&h[tt * kRxBins + ((c[k] >> shift) & (kRxBins - 1))], 1);
     }
     __syncthreads();
-    table[(int64_t)threadIdx.x * tiles + tile] = h[threadIdx.x];
+#pragma unroll
+    for (int tt = 0; tt < kRxHistTiles; ++tt)
+        if (tb + tt < tiles) table[(int64_t)threadIdx.x * tiles + tb + tt] = h[tt * kRxBins + threadIdx.x];
 }
 
 // ------------------------------------------------------------------ scan
@@ -229,16 +247,31 @@ k_rx_scatter(int64_t nnz, int64_t tiles, int shift, const int* __restrict__ col_
 
 // From the columns in sorted order: ccp[j] is the first position whose
 // column is at least j; the last position also fills the columns after it,
-// and ccp[n] = nnz.
+// and ccp[n] = nnz.  Each thread takes 8 consecutive positions.
 __global__ void __launch_bounds__(kBlock)
 k_rx_ccp(int n, int64_t nnz, const int* __restrict__ scol, int* __restrict__ ccp) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= nnz) return;
-    const int c = scol[i];
-    const int pc = i > 0 ? scol[i - 1] : -1;
-    for (int j = pc + 1; j <= c; ++j) ccp[j] = (int)i;
-    if (i == nnz - 1)
-        for (int j = c + 1; j <= n; ++j) ccp[j] = (int)nnz;
+    static_assert(kRxCcpPer == 8, "two 16-byte loads per thread");
+    const int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * kRxCcpPer;
+    if (i0 >= nnz) return;
+    int c[kRxCcpPer];
+    if (i0 + kRxCcpPer <= nnz) {
+        const int4 a = *reinterpret_cast<const int4*>(scol + i0);
+        const int4 b = *reinterpret_cast<const int4*>(scol + i0 + 4);
+        c[0] = a.x; c[1] = a.y; c[2] = a.z; c[3] = a.w; c[4] = b.x; c[5] = b.y; c[6] = b.z; c[7] = b.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < kRxCcpPer; ++k) c[k] = i0 + k < nnz ? scol[i0 + k] : 0;
+    }
+    int pc = i0 > 0 ? scol[i0 - 1] : -1;
+#pragma unroll
+    for (int k = 0; k < kRxCcpPer; ++k) {
+        const int64_t i = i0 + k;
+        if (i >= nnz) break;
+        for (int j = pc + 1; j <= c[k]; ++j) ccp[j] = (int)i;
+        pc = c[k];
+    }
+    if (i0 + kRxCcpPer >= nnz)
+        for (int j = pc + 1; j <= n; ++j) ccp[j] = (int)nnz;
 }
 
 // The longest column, and the total, into the summary (zeroed before).
@@ -282,8 +315,8 @@ static hipError_t run_radix(const RadixGeom& g, int n, int64_t nnz, const int* i
         int* cout = into_y ? ws.ycol : ws.xcol;
         int* rout = last ? irow_t : (into_y ? ws.yrow : ws.xrow);
         V* vout = last ? static_cast<V*>(val_t) : static_cast<V*>(into_y ? ws.yval : ws.xval);
-        hipLaunchKernelGGL(k_rx_hist, dim3((unsigned)g.tiles), dim3(kRxThreads), 0, s, nnz, g.tiles, shift, cin,
-                           ws.table);
+        hipLaunchKernelGGL(k_rx_hist, dim3((unsigned)((g.tiles + kRxHistTiles - 1) / kRxHistTiles)), dim3(kRxThreads),
+                           0, s, nnz, g.tiles, shift, cin, ws.table);
         hipLaunchKernelGGL(k_rx_scan_reduce, dim3((unsigned)g.chunks), dim3(kRxThreads), 0, s, g.table, ws.table,
                            ws.csum);
         hipLaunchKernelGGL(k_rx_scan_top, dim3(1), dim3(kRxThreads), 0, s, g.chunks, ws.csum);
@@ -297,7 +330,9 @@ static hipError_t run_radix(const RadixGeom& g, int n, int64_t nnz, const int* i
         vin = vout;
         scol = cout;
     }
-    hipLaunchKernelGGL(k_rx_ccp, dim3((unsigned)((nnz + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, nnz, scol, ccp);
+    const int64_t per_block = (int64_t)kBlock * kRxCcpPer;
+    hipLaunchKernelGGL(k_rx_ccp, dim3((unsigned)((nnz + per_block - 1) / per_block)), dim3(kBlock), 0, s, n, nnz, scol,
+                       ccp);
     const int grid = (int)std::min<int64_t>(1024, ((int64_t)n + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_rx_summary, dim3((unsigned)std::max(grid, 1)), dim3(kBlock), 0, s, n, ccp, sum);
     return hipGetLastError();
