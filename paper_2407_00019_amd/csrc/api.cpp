@@ -75,7 +75,7 @@ int ccs_route(int32_t n, int32_t bw, int32_t max_row, int alg) {
 // table or the sort route's keys and merge scratch.
 struct CcsWs {
     size_t cursor, bsum, mid, lng, ext, sum, info, keys, tmp;   // sort and windowed routes
-    size_t wtable, bstart, wkey, wval;                        // windowed route (overlays keys)
+    size_t wtable, bstart, wflag, wkey, wval;                 // windowed route (overlays keys)
     size_t table, csum, bkey, bval;                           // bucketed route
     size_t xcol, xrow, xval, ycol, yrow, yval;                // radix route (with table, csum, sum)
     size_t total;
@@ -128,6 +128,7 @@ CcsWs ccs_ws(int32_t n, int64_t nnz, int vb, int32_t bw, int32_t max_row, int al
         size_t q = o;
         w.wtable = q; q += round_up((size_t)g.table * 4, kAlign);
         w.bstart = q; q += round_up(((size_t)g.nb + 1) * 4, kAlign);
+        w.wflag = q;  q += round_up((size_t)g.stretches * 4, kAlign);
         w.wkey = q;   q += round_up((size_t)nnz * 4, kAlign);
         w.wval = q;   q += round_up((size_t)nnz * vb, kAlign);
         win_bytes = q - o;
@@ -137,31 +138,71 @@ CcsWs ccs_ws(int32_t n, int64_t nnz, int vb, int32_t bw, int32_t max_row, int al
     return w;
 }
 
-// Pinned host records for the row statistics of spmv_plan_create: taken
-// for the call and returned after it, so their number is the most calls
-// that ever ran at once, whatever threads made them.
-std::mutex g_pinned_mu;
-std::vector<RowStats*> g_pinned_free;
+// Pinned host records for the small results a call reads back (the row
+// statistics of spmv_plan_create, the summaries of csr_to_ccs): taken for
+// the call and returned after it, so their number is the most calls that
+// ever ran at once, whatever threads made them.  A copy into pinned memory
+// is one DMA with no staging, so a call's read-backs queue behind its
+// kernels and one synchronisation ends them all.
+struct HostRec {
+    alignas(64) unsigned char bytes[64];
+};
+static_assert(sizeof(RowStats) <= sizeof(HostRec), "row statistics fit a record");
+static_assert(sizeof(ColSummary) + sizeof(WccsInfo) <= sizeof(HostRec), "CCS summaries fit a record");
 
-RowStats* pinned_take() {
+std::mutex g_pinned_mu;
+std::vector<HostRec*> g_pinned_free;
+
+HostRec* pinned_take() {
     {
         std::lock_guard<std::mutex> g(g_pinned_mu);
         if (!g_pinned_free.empty()) {
-            RowStats* r = g_pinned_free.back();
+            HostRec* r = g_pinned_free.back();
             g_pinned_free.pop_back();
             return r;
         }
     }
-    RowStats* r = nullptr;
-    if (hipHostMalloc(reinterpret_cast<void**>(&r), sizeof(RowStats), hipHostMallocCoherent) != hipSuccess)
+    HostRec* r = nullptr;
+    if (hipHostMalloc(reinterpret_cast<void**>(&r), sizeof(HostRec), hipHostMallocCoherent) != hipSuccess)
         return nullptr;
     return r;
 }
 
-void pinned_give(RowStats* r) {
+void pinned_give(HostRec* r) {
     std::lock_guard<std::mutex> g(g_pinned_mu);
     g_pinned_free.push_back(r);
 }
+
+// A record held for one call: returned on every way out of it, after the
+// stream has passed any copy still bound for it.
+struct HeldRec {
+    HostRec* r = pinned_take();
+    hipStream_t s;
+    bool pending = false;
+    explicit HeldRec(hipStream_t st) : s(st) {}
+    HeldRec(const HeldRec&) = delete;
+    HeldRec& operator=(const HeldRec&) = delete;
+    ~HeldRec() {
+        if (!r) return;
+        if (pending) (void)hipStreamSynchronize(s);
+        pinned_give(r);
+    }
+    // copies bytes from the device into the record at offset `at`
+    hipError_t fetch(size_t at, const void* src, size_t bytes) {
+        pending = true;
+        return hipMemcpyAsync(r->bytes + at, src, bytes, hipMemcpyDeviceToHost, s);
+    }
+    hipError_t wait() {
+        const hipError_t e = hipStreamSynchronize(s);
+        if (e == hipSuccess) pending = false;
+        return e;
+    }
+    template <typename T> T get(size_t at) const {
+        T v;
+        std::memcpy(&v, r->bytes + at, sizeof(T));
+        return v;
+    }
+};
 
 bool check_buffers(const spmv_buffers* out, int count, const spmv_sizes& need) {
     if (!out) return false;
@@ -224,17 +265,18 @@ SPMV_API spmv_status spmv_plan_create(spmv_plan** plan, int32_t n, int64_t nnz, 
     if (!p) return SPMV_E_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     // a pinned record receives the statistics straight from the kernel
-    RowStats* pinned = pinned_take();
-    if (!pinned) {
+    HostRec* rec = pinned_take();
+    if (!rec) {
         delete p;
         return SPMV_E_HIP;
     }
+    RowStats* pinned = reinterpret_cast<RowStats*>(rec->bytes);
     spmv_status st = plan_begin(p, n, nnz, irp, icol, val, val_type, plan_work, plan_work_bytes, pinned, s);
     if (st == SPMV_OK && hipStreamSynchronize(s) != hipSuccess) st = SPMV_E_HIP;
     if (st == SPMV_OK) st = plan_finish(p, *pinned);
     // the record goes back only once nothing on the stream can still write it
     if (st == SPMV_E_HIP) (void)hipStreamSynchronize(s);
-    pinned_give(pinned);
+    pinned_give(rec);
     if (st != SPMV_OK) { delete p; return st; }
     *plan = p;
     return SPMV_OK;
@@ -372,6 +414,10 @@ SPMV_API spmv_status csr_to_ccs(spmv_plan* p, const spmv_buffers* out, void* wor
     void* val_t = out->ptr[2];
     ColSummary* dsum = reinterpret_cast<ColSummary*>(base + w.sum);
     ColSummary cs{};
+    // the summaries come back through one pinned record: [ColSummary | WccsInfo]
+    HeldRec rec(s);
+    if (!rec.r) return SPMV_E_HIP;
+    constexpr size_t kAtInfo = sizeof(ColSummary);
     auto built = [&]() {
         p->ccp = ccp; p->irow_t = irow_t; p->val_t = val_t; p->has_ccs = true;
         p->st.max_col = cs.max_len;
@@ -396,8 +442,9 @@ SPMV_API spmv_status csr_to_ccs(spmv_plan* p, const spmv_buffers* out, void* wor
         rw.csum = reinterpret_cast<int32_t*>(base + w.csum);
         if (p->nnz == 0) HIP_TRY(p, launch_fill_zero(ccp, ((int64_t)p->n + 1) * 4, s));
         HIP_TRY(p, launch_ccs_radix(g, p->n, p->nnz, p->irp, p->icol, p->val, vb, rw, ccp, irow_t, val_t, dsum, s));
-        HIP_TRY(p, hipMemcpyAsync(&cs, dsum, sizeof(cs), hipMemcpyDeviceToHost, s));
-        HIP_TRY(p, hipStreamSynchronize(s));
+        HIP_TRY(p, rec.fetch(0, dsum, sizeof(cs)));
+        HIP_TRY(p, rec.wait());
+        cs = rec.get<ColSummary>(0);
         if ((int64_t)cs.total != p->nnz) {
             p->err = "column pointer does not end at nnz";
             return SPMV_E_HIP;
@@ -414,8 +461,9 @@ SPMV_API spmv_status csr_to_ccs(spmv_plan* p, const spmv_buffers* out, void* wor
                                        reinterpret_cast<int32_t*>(base + w.csum),
                                        reinterpret_cast<uint32_t*>(base + w.bkey), base + w.bval, ccp, irow_t, val_t,
                                        dsum, s));
-        HIP_TRY(p, hipMemcpyAsync(&cs, dsum, sizeof(cs), hipMemcpyDeviceToHost, s));
-        HIP_TRY(p, hipStreamSynchronize(s));
+        HIP_TRY(p, rec.fetch(0, dsum, sizeof(cs)));
+        HIP_TRY(p, rec.wait());
+        cs = rec.get<ColSummary>(0);
         if ((int64_t)cs.total != p->nnz) {
             p->err = "column-block counts do not add up to nnz";
             return SPMV_E_HIP;
@@ -439,14 +487,17 @@ SPMV_API spmv_status csr_to_ccs(spmv_plan* p, const spmv_buffers* out, void* wor
         int32_t* bstart = reinterpret_cast<int32_t*>(base + w.bstart);
         WccsInfo* dinfo = reinterpret_cast<WccsInfo*>(base + w.info);
         WccsInfo wi{};
-        HIP_TRY(p, launch_wccs_front(g, p->n, bw, p->irp, p->icol, table, cursor, dinfo, s));
-        HIP_TRY(p, launch_col_scan(g.nb, cursor, bstart, cursor, bsum, nullptr, nullptr, dsum, s));
+        HIP_TRY(p, launch_wccs_front(g, p->n, bw, p->irp, p->icol, table, cursor,
+                                     reinterpret_cast<int32_t*>(base + w.wflag), dinfo, s));
+        HIP_TRY(p, launch_wccs_scan(g, cursor, bstart, bsum, dsum, s));
         HIP_TRY(p, launch_wccs_back(g, p->n, bw, vb, p->irp, p->icol, p->val, table, bstart,
                                     reinterpret_cast<uint32_t*>(base + w.wkey), base + w.wval, ccp, irow_t, val_t,
                                     dinfo, s));
-        HIP_TRY(p, hipMemcpyAsync(&cs, dsum, sizeof(cs), hipMemcpyDeviceToHost, s));
-        HIP_TRY(p, hipMemcpyAsync(&wi, dinfo, sizeof(wi), hipMemcpyDeviceToHost, s));
-        HIP_TRY(p, hipStreamSynchronize(s));
+        HIP_TRY(p, rec.fetch(0, dsum, sizeof(cs)));
+        HIP_TRY(p, rec.fetch(kAtInfo, dinfo, sizeof(wi)));
+        HIP_TRY(p, rec.wait());
+        cs = rec.get<ColSummary>(0);
+        wi = rec.get<WccsInfo>(kAtInfo);
         if (wi.flags & kWccsOutside) {
             p->err = "a column index lies outside the bandwidth measured when the plan was made";
             return SPMV_E_MATRIX;
@@ -462,8 +513,9 @@ SPMV_API spmv_status csr_to_ccs(spmv_plan* p, const spmv_buffers* out, void* wor
     HIP_TRY(p, hipMemsetAsync(cursor, 0, (size_t)p->n * 4, s));
     if (p->nnz > 0) HIP_TRY(p, launch_col_count(p->n, p->st.bandwidth, p->irp, p->icol, cursor, s));
     HIP_TRY(p, launch_col_scan(p->n, cursor, ccp, cursor, bsum, mid, lng, dsum, s));
-    HIP_TRY(p, hipMemcpyAsync(&cs, dsum, sizeof(cs), hipMemcpyDeviceToHost, s));
-    HIP_TRY(p, hipStreamSynchronize(s));
+    HIP_TRY(p, rec.fetch(0, dsum, sizeof(cs)));
+    HIP_TRY(p, rec.wait());
+    cs = rec.get<ColSummary>(0);
     if ((int64_t)cs.total != p->nnz) {
         p->err = "column counts do not add up to nnz";
         return SPMV_E_HIP;

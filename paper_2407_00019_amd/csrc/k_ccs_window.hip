@@ -8,8 +8,9 @@
 // blocks stays small.  Inside a tile each wave owns one consecutive stretch
 // of the tile's entries.
 //
-//   count       per tile: entries per (wave stretch, window block).
-//   blocks      one thread per block: a walk over the tiles whose window
+//   count       per wave stretch (one wave per workgroup): entries per
+//               window block.
+//   blocks      one wave per block: a scan over the tiles whose window
 //               covers the block, in tile order and wave order inside a
 //               tile, turns the counts into each stretch's start inside the
 //               block and sums the block's length; the block starts follow
@@ -40,13 +41,15 @@ constexpr int kBcCols = 1 << kBcBits;
 constexpr int kBcRows = 2048;              // rows per tile
 constexpr int kBcWaves = 16;               // waves per tile (count, distribute)
 constexpr int kBcThreads = kBcWaves * kWave;
-constexpr int kBcUnroll = 8;               // groups of 64 entries loaded ahead
+constexpr int kBcUnroll = 8;               // groups of 64 entries (count: of 64 quads) loaded ahead
 constexpr int kPlWaves = 8;                // place: waves per block
 constexpr int kPlThreads = kPlWaves * kWave;
 constexpr int kPlStageBytes = 36 * 1024;   // place: LDS stage of rows and values
 constexpr int kPlBlocks = 4;               // place: blocks per workgroup
 constexpr int kPlPer = 4;                  // place: entries per lane and block held in registers
-constexpr int kBcMaxWindowBlocks = 1536;   // count / distribute LDS: 16 waves x 1536 counters = 96 KiB
+constexpr int kBcMaxWindowBlocks = 1536;   // distribute LDS: 16 waves x 1536 counters = 96 KiB
+constexpr int kBkWaves = 8;                // blocks kernel: waves per workgroup of 64 blocks
+constexpr int kBkMaxTiles = 64;            // blocks kernel: tiles whose window can hold one of its 64 blocks
 
 __device__ __forceinline__ int bc_lo(int t, int bw) { return max(0, t * kBcRows - bw); }
 __device__ __forceinline__ int bc_hi(int n, int t, int bw) {
@@ -73,78 +76,225 @@ WccsGeom wccs_geom(int n, int bw, int max_row) {
     g.nb = (n + kBcCols - 1) / kBcCols;
     const int64_t wmax = std::min<int64_t>(n, (int64_t)kBcRows + 2 * (int64_t)std::max(bw, 0));
     g.nwbmax = (int)((wmax + kBcCols - 1) / kBcCols) + 1;
-    g.table = (int64_t)g.tiles * kBcWaves * g.nwbmax;
+    g.stretches = (int64_t)g.tiles * kBcWaves;
+    g.table = g.stretches * g.nwbmax;
     int bits = 1;
     while ((1 << bits) < g.nwbmax) ++bits;
     g.wb_bits = bits;
     // the packed key keeps the row in 32 - kBcBits bits
-    g.usable = bw >= 0 && n <= (1 << (32 - kBcBits)) && g.nwbmax <= kBcMaxWindowBlocks;
+    // tiles a workgroup of the blocks kernel walks (64 blocks): bounded by
+    // the window limit already, checked against its LDS table all the same
+    const int64_t span = std::min<int64_t>(g.tiles, (4095 + 2 * (int64_t)std::max(bw, 0) + 2 * kBcRows - 1) / kBcRows + 2);
+    g.usable = bw >= 0 && n <= (1 << (32 - kBcBits)) && g.nwbmax <= kBcMaxWindowBlocks && span <= kBkMaxTiles;
     return g;
 }
 
 // ------------------------------------------------------------------ count
 
-__global__ void __launch_bounds__(kBcThreads)
+__global__ void __launch_bounds__(kWave)
 k_bcs_count(int n, int bw, int nwbmax, const int* __restrict__ irp, const int* __restrict__ icol,
-            int* __restrict__ table, WccsInfo* __restrict__ info) {
-    extern __shared__ int lds_c[];   // kBcWaves x nwbmax
-    const int t = (int)xcd_block(blockIdx.x, gridDim.x);
+            int* __restrict__ table, int* __restrict__ sflag, WccsInfo* __restrict__ info) {
+    extern __shared__ int lds_c[];   // nwbmax
+    const int tw = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int t = tw / kBcWaves;
     const int r0 = t * kBcRows, r1 = min(n, r0 + kBcRows);
     const int b0 = bc_lo(t, bw) >> kBcBits, b1 = (bc_hi(n, t, bw) - 1) >> kBcBits;
     const int nwb = b1 - b0 + 1;
-    const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-    for (int i = threadIdx.x; i < kBcWaves * nwb; i += kBcThreads) lds_c[(i / nwb) * nwbmax + i % nwb] = 0;
+    const int w = tw % kBcWaves, lane = threadIdx.x & (kWave - 1);
+    for (int i = threadIdx.x; i < nwb; i += kWave) lds_c[i] = 0;
     __syncthreads();
     int ws, we;
     stretch(irp[r0], irp[r1], kBcWaves, w, ws, we);
-    int* mine = lds_c + w * nwbmax;
+    int* mine = lds_c;
     bool outside = false;
-    for (int base = ws; base < we; base += kWave * kBcUnroll) {
-        int c[kBcUnroll];
-#pragma unroll
-        for (int u = 0; u < kBcUnroll; ++u) c[u] = icol[min(base + u * kWave + lane, we - 1)];
+    // counting needs no order: a lane takes aligned quads of the stretch by
+    // 16-byte loads (the head and tail entries one by one) and adds one LDS
+    // atomic per run of entries of equal block it meets
+    int cur = -1, cnt = 0;
+    auto take = [&](int c) {
+        const unsigned wb = (unsigned)((c >> kBcBits) - b0);
+        if (wb >= (unsigned)nwb) { outside = true; return; }
+        if ((int)wb != cur) {
+            if (cnt) atomicAdd(&mine[cur], cnt);
+            cur = (int)wb;
+            cnt = 0;
+        }
+        ++cnt;
+    };
+    const int qa = min(we, (ws + 3) & ~3), qb = max(qa, we & ~3);
+    if (lane < qa - ws) take(icol[ws + lane]);
+    if (lane < we - qb) take(icol[qb + lane]);
+    const int4* q4 = reinterpret_cast<const int4*>(icol + qa);
+    const int nq = (qb - qa) >> 2;
+    for (int base = 0; base < nq; base += kWave * kBcUnroll) {
+        int4 v[kBcUnroll];
 #pragma unroll
         for (int u = 0; u < kBcUnroll; ++u) {
-            if (base + u * kWave + lane >= we) continue;
-            const unsigned wb = (unsigned)((c[u] >> kBcBits) - b0);
-            if (wb < (unsigned)nwb) atomicAdd(&mine[wb], 1);
-            else outside = true;
+            const int q = base + u * kWave + lane;
+            v[u] = q < nq ? q4[q] : make_int4(-1, -1, -1, -1);
+        }
+#pragma unroll
+        for (int u = 0; u < kBcUnroll; ++u) {
+            if (base + u * kWave + lane >= nq) break;
+            take(v[u].x); take(v[u].y); take(v[u].z); take(v[u].w);
         }
     }
-    if (outside) atomicOr(&info->flags, kWccsOutside);
-    __syncthreads();
-    int* trow = table + (int64_t)t * kBcWaves * nwbmax;
-    for (int i = threadIdx.x; i < kBcWaves * nwb; i += kBcThreads) {
-        const int ww = i / nwb, wb = i % nwb;
-        trow[ww * nwbmax + wb] = lds_c[ww * nwbmax + wb];
+    if (cnt) atomicAdd(&mine[cur], cnt);
+    // every stretch writes its flag, so nothing needs clearing first; the
+    // route's record is cleared here, before the blocks kernel flags it and
+    // the placement raises its longest column
+    const bool any_out = __ballot(outside) != 0;
+    if (lane == 0) {
+        sflag[(int64_t)t * kBcWaves + w] = any_out ? 1 : 0;
+        if (tw == 0) { info->flags = 0; info->kmax = 0; }
     }
+    __syncthreads();
+    int* trow = table + ((int64_t)t * kBcWaves + w) * nwbmax;
+    for (int i = threadIdx.x; i < nwb; i += kWave) trow[i] = lds_c[i];
 }
 
 // ----------------------------------------------------------------- blocks
 
-__global__ void __launch_bounds__(kBlock)
-k_bcs_blocks(int n, int bw, int tiles, int nb, int nwbmax, int* __restrict__ table, int* __restrict__ bcnt) {
-    const int b = (int)blockIdx.x * kBlock + (int)threadIdx.x;
-    if (b >= nb) return;
-    // tiles whose window blocks [lo / 64, (hi - 1) / 64] hold b: a range a
-    // little wider than needed, checked per tile
-    const int64_t c0 = (int64_t)b * kBcCols;
-    const int64_t a = c0 - bw - kBcRows;
-    const int tlo = a <= 0 ? 0 : (int)(a / kBcRows);
-    const int thi = (int)min64((int64_t)tiles - 1, (c0 + kBcCols - 1 + bw) / kBcRows);
-    int run = 0;
-    for (int t = tlo; t <= thi; ++t) {
+// Tiles whose window can hold a block of [g * 64, g * 64 + 64): a range a
+// little wider than needed, checked per tile.
+__device__ __forceinline__ void bk_tiles(int n, int bw, int tiles, int g, int& tlo, int& thi) {
+    const int64_t cf = (int64_t)g * kWave * kBcCols;
+    const int64_t cl = min64((int64_t)n, cf + (int64_t)kWave * kBcCols) - 1;
+    const int64_t a = cf - bw - kBcRows;
+    tlo = a <= 0 ? 0 : (int)(a / kBcRows);
+    thi = (int)min64((int64_t)tiles - 1, (cl + bw) / kBcRows);
+}
+
+// Lane j owns block g * 64 + j.  First the block's count in every tile
+// (summed over the tile's waves), then their exclusive scan in tile order,
+// then each wave stretch's start inside the block, in tile order and wave
+// order inside a tile; the block starts follow by the shared scan kernels.
+__global__ void __launch_bounds__(kBkWaves * kWave)
+k_bcs_blocks(int n, int bw, int tiles, int nb, int nwbmax, int64_t stretches, int* __restrict__ table,
+             int* __restrict__ bcnt, const int* __restrict__ sflag, WccsInfo* __restrict__ info) {
+    __shared__ int tot[kBkMaxTiles][kWave];
+    {
+        bool out = false;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < stretches;
+             i += (int64_t)gridDim.x * blockDim.x)
+            out |= sflag[i] != 0;
+        if (__ballot(out) != 0 && (threadIdx.x & (kWave - 1)) == 0) atomicOr(&info->flags, kWccsOutside);
+    }
+    const int g = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    const int b = g * kWave + lane;
+    int tlo, thi;
+    bk_tiles(n, bw, tiles, g, tlo, thi);
+    for (int t = tlo + w; t <= thi; t += kBkWaves) {
         const int b0 = bc_lo(t, bw) >> kBcBits, b1 = (bc_hi(n, t, bw) - 1) >> kBcBits;
-        if (b < b0 || b > b1) continue;
-        int* p = table + (int64_t)t * kBcWaves * nwbmax + (b - b0);
-#pragma unroll 4
-        for (int w = 0; w < kBcWaves; ++w) {
-            const int v = p[w * nwbmax];
-            p[w * nwbmax] = run;
+        int sum = 0;
+        if (b < nb && b >= b0 && b <= b1) {
+            const int* p = table + (int64_t)t * kBcWaves * nwbmax + (b - b0);
+#pragma unroll
+            for (int ww = 0; ww < kBcWaves; ++ww) sum += p[ww * nwbmax];
+        }
+        tot[t - tlo][lane] = sum;
+    }
+    __syncthreads();
+    if (w == 0) {
+        int run = 0;
+        for (int t = tlo; t <= thi; ++t) {
+            const int v = tot[t - tlo][lane];
+            tot[t - tlo][lane] = run;
             run += v;
         }
+        if (b < nb) bcnt[b] = run;
     }
-    bcnt[b] = run;
+    __syncthreads();
+    for (int t = tlo + w; t <= thi; t += kBkWaves) {
+        const int b0 = bc_lo(t, bw) >> kBcBits, b1 = (bc_hi(n, t, bw) - 1) >> kBcBits;
+        if (b >= nb || b < b0 || b > b1) continue;
+        int* p = table + (int64_t)t * kBcWaves * nwbmax + (b - b0);
+        int run = tot[t - tlo][lane];
+        int v[kBcWaves];
+#pragma unroll
+        for (int ww = 0; ww < kBcWaves; ++ww) v[ww] = p[ww * nwbmax];
+#pragma unroll
+        for (int ww = 0; ww < kBcWaves; ++ww) {
+            p[ww * nwbmax] = run;
+            run += v[ww];
+        }
+    }
+}
+
+// ------------------------------------------------------------------- scan
+
+constexpr int kBsThreads = 1024;
+constexpr int kBsPer = 16;                        // counts a thread takes per chunk (four 16-byte loads)
+constexpr int kBsChunk = kBsThreads * kBsPer;
+constexpr int kBsMax = 8 * kBsChunk;              // block counts scanned by one workgroup
+
+// Block starts by one workgroup, a chunk of 16,384 counts at a time: each
+// thread loads 16 consecutive counts, a workgroup scan of the threads' sums
+// gives each its start, and the chunk's total carries into the next.
+__global__ void __launch_bounds__(kBsThreads)
+k_bcs_scan(int nb, const int* __restrict__ bcnt, int* __restrict__ bstart, ColSummary* __restrict__ sum) {
+    __shared__ int wtot[kBsThreads / kWave];
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+    int carry = 0;
+    for (int c0 = 0; c0 < nb; c0 += kBsChunk) {
+        const int i0 = c0 + t * kBsPer;
+        const bool whole = i0 + kBsPer <= nb;
+        int v[kBsPer];
+        if (whole) {
+            const int4* p = reinterpret_cast<const int4*>(bcnt + i0);
+#pragma unroll
+            for (int q = 0; q < kBsPer / 4; ++q) {
+                const int4 x = p[q];
+                v[4 * q] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kBsPer; ++k) v[k] = i0 + k < nb ? bcnt[i0 + k] : 0;
+        }
+        int local = 0;
+#pragma unroll
+        for (int k = 0; k < kBsPer; ++k) local += v[k];
+        int incl = local;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int y = __shfl_up(incl, off, kWave);
+            if (lane >= off) incl += y;
+        }
+        if (lane == kWave - 1) wtot[w] = incl;
+        __syncthreads();
+        int before = 0, total = 0;
+#pragma unroll
+        for (int k = 0; k < kBsThreads / kWave; ++k) {
+            before += k < w ? wtot[k] : 0;
+            total += wtot[k];
+        }
+        int run = carry + before + incl - local;
+#pragma unroll
+        for (int k = 0; k < kBsPer; ++k) {
+            const int x = v[k];
+            v[k] = run;
+            run += x;
+        }
+        if (whole) {
+            int4* p = reinterpret_cast<int4*>(bstart + i0);
+#pragma unroll
+            for (int q = 0; q < kBsPer / 4; ++q) p[q] = make_int4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < kBsPer; ++k)
+                if (i0 + k < nb) bstart[i0 + k] = v[k];
+        }
+        carry += total;
+        __syncthreads();   // wtot is read above before the next chunk writes it
+    }
+    if (t == 0) {
+        bstart[nb] = carry;
+        sum->total = carry;
+        sum->max_len = 0;
+        sum->n_mid = 0;
+        sum->n_long = 0;
+    }
 }
 
 // ------------------------------------------------------------- distribute
@@ -373,18 +523,21 @@ k_bcs_place(int n, int nb, const int* __restrict__ bstart, const uint32_t* __res
 // ---------------------------------------------------------------- launchers
 
 hipError_t launch_wccs_front(const WccsGeom& g, int n, int bw, const int* irp, const int* icol, int* table,
-                             int* bcnt, WccsInfo* info, hipStream_t s) {
-    hipError_t e = launch_fill_zero(info, sizeof(WccsInfo), s);
+                             int* bcnt, int* sflag, WccsInfo* info, hipStream_t s) {
+    const size_t lds = (size_t)g.nwbmax * 4;
+    hipLaunchKernelGGL(k_bcs_count, dim3((unsigned)g.stretches), dim3(kWave), lds, s, n, bw, g.nwbmax, irp, icol,
+                       table, sflag, info);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t lds = (size_t)kBcWaves * g.nwbmax * 4;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bcs_count), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bcs_count, dim3((unsigned)g.tiles), dim3(kBcThreads), lds, s, n, bw, g.nwbmax, irp, icol,
-                       table, info);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bcs_blocks, dim3((unsigned)((g.nb + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, bw,
-                       g.tiles, g.nb, g.nwbmax, table, bcnt);
+    const int groups = (g.nb + kWave - 1) / kWave;
+    hipLaunchKernelGGL(k_bcs_blocks, dim3((unsigned)groups), dim3(kBkWaves * kWave), 0, s, n, bw, g.tiles, g.nb,
+                       g.nwbmax, g.stretches, table, bcnt, sflag, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_wccs_scan(const WccsGeom& g, int* bcnt, int* bstart, int* bsum, ColSummary* sum, hipStream_t s) {
+    if (g.nb > kBsMax) return launch_col_scan(g.nb, bcnt, bstart, bcnt, bsum, nullptr, nullptr, sum, s);
+    hipLaunchKernelGGL(k_bcs_scan, dim3(1), dim3(kBsThreads), 0, s, g.nb, bcnt, bstart, sum);
     return hipGetLastError();
 }
 

@@ -108,10 +108,11 @@ hipError_t launch_ccs_radix(const RadixGeom& g, int n, int64_t nnz, const int* i
 // blocks, then a stable per-block placement by column staged in LDS.
 struct WccsGeom {
     int rows, tiles;       // rows per tile, tiles
-    int nb;                // 128-column blocks
+    int nb;                // 64-column blocks
     int nwbmax;            // window blocks of the widest window
     int wb_bits;           // bits of a window block index
-    int64_t table;         // table counts: tiles x waves x nwbmax
+    int64_t stretches;     // wave stretches: tiles x waves
+    int64_t table;         // table counts: stretches x nwbmax
     bool usable;           // the window fits the kernels' LDS and n fits the packed key
 };
 constexpr uint32_t kWccsOutside = 1;    // an entry outside its tile's window (CRS changed since the plan)
@@ -120,9 +121,15 @@ struct WccsInfo {
     int32_t kmax;          // the longest column
 };
 WccsGeom wccs_geom(int n, int bw, int max_row);
-// counts and the per-block walk; bcnt[b] receives the length of block b
+// counts and the per-block walk; bcnt[b] receives the length of block b,
+// sflag[stretches] the per-stretch flags of entries outside the window (info
+// is cleared, then flagged, on the way)
 hipError_t launch_wccs_front(const WccsGeom& g, int n, int bw, const int* irp, const int* icol, int* table,
-                             int* bcnt, WccsInfo* info, hipStream_t s);
+                             int* bcnt, int* sflag, WccsInfo* info, hipStream_t s);
+// bstart[nb + 1] = exclusive scan of bcnt, sum->total = the last start; bsum
+// is the shared scan's scratch (col_scan_bsum_count(nb) x 2 ints) for block
+// counts too many for one workgroup
+hipError_t launch_wccs_scan(const WccsGeom& g, int* bcnt, int* bstart, int* bsum, ColSummary* sum, hipStream_t s);
 // distribution (key[nnz], sval[nnz] staging) and placement; bstart[nb + 1]
 // holds the scanned block lengths
 hipError_t launch_wccs_back(const WccsGeom& g, int n, int bw, int vbytes, const int* irp, const int* icol,

@@ -317,6 +317,26 @@ def test_ccs_with_a_long_column_at_large_n(n):
     plan.close()
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("n", [64 * 131072, 64 * 131072 + 3001])
+def test_ccs_banded_at_the_block_scan_limit(n):
+    """The banded CRS -> CCS at n = 8,388,608 (131,072 column blocks: the most
+    one workgroup scans, in eight chunks) and 3,001 rows past it (the shared
+    multi-kernel scan takes the block counts): the oracle's arrays bit for
+    bit."""
+    spmvat = lib_ready()
+    m = gen.banded(n, 2, 41)
+    irp, icol, val = to_dev(m)
+    plan = spmvat.Plan(irp, icol, val)
+    ccp, irow_t, val_t = plan.to_ccs(algorithm=spmvat.CCS_BANDED)
+    o_ccp, o_irow_t, o_val_t = oracle.csr_to_ccs(m.n, m.irp, m.icol, m.val)
+    assert np.array_equal(host(ccp), o_ccp)
+    assert np.array_equal(host(irow_t), o_irow_t)
+    assert np.array_equal(bits(host(val_t)), bits(o_val_t))
+    assert plan.stats.max_col == int(np.diff(o_ccp).max())
+    plan.close()
+
+
 def test_error_paths_leave_the_plan_usable():
     import torch
     spmvat = lib_ready()
