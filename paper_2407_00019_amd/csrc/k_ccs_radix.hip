@@ -140,18 +140,41 @@ k_rx_scan_apply(int64_t m, int* __restrict__ a, const int* __restrict__ csum) {
     __shared__ int wsum[kRxWaves];
     constexpr int kPer = kRxScan / kRxThreads;
     const int64_t c0 = (int64_t)blockIdx.x * kRxScan + (int64_t)threadIdx.x * kPer;
+    static_assert(kPer % 4 == 0, "a thread's counts are whole 16-byte vectors");
+    // a thread's run by 16-byte loads and stores (the table is 256-byte
+    // aligned and runs start at multiples of kPer); the last run of the
+    // table one count at a time
+    const bool whole = c0 + kPer <= m;
     int v[kPer];
+    if (whole) {
+        const int4* p = reinterpret_cast<const int4*>(a + c0);
+#pragma unroll
+        for (int q = 0; q < kPer / 4; ++q) {
+            const int4 x = p[q];
+            v[4 * q] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) v[k] = c0 + k < m ? a[c0 + k] : 0;
+    }
     int s = 0;
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        v[k] = c0 + k < m ? a[c0 + k] : 0;
-        s += v[k];
-    }
+    for (int k = 0; k < kPer; ++k) s += v[k];
     int run = csum[blockIdx.x] + rx_block_scan(s, wsum, nullptr);
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-        if (c0 + k < m) a[c0 + k] = run;
-        run += v[k];
+        const int x = v[k];
+        v[k] = run;
+        run += x;
+    }
+    if (whole) {
+        int4* p = reinterpret_cast<int4*>(a + c0);
+#pragma unroll
+        for (int q = 0; q < kPer / 4; ++q) p[q] = make_int4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kPer; ++k)
+            if (c0 + k < m) a[c0 + k] = v[k];
     }
 }
 

@@ -40,6 +40,7 @@ constexpr int kPgPer = kPgWindow / kBlock;   // window pages per thread in the n
 static_assert(kPgWindow % kBlock == 0, "the numbering scan gives each thread whole pages");
 constexpr int kEcVec = 4;                    // ELL-Column: adjacent columns per thread (n % 4 == 0)
 constexpr int kEcAccBytes = 32768;           // its partial sums: 64 binary64 / 128 binary32 pages
+constexpr int kEcHeld = 32;                  // ELL-Column widths whose rows stay in registers between the passes
 constexpr int kEc1AccBytes = 20480;          // one column per thread: 40 / 80 pages
 constexpr int kCcVec = 4;                    // COO-Column: consecutive entries per thread and step
 constexpr int kCcChunk = 4096;               // entries per workgroup
@@ -147,6 +148,14 @@ __device__ __forceinline__ void add_row(S& sm, int lo, int nwin, int r, X v, X* 
     else add_global(&y[r], v);
 }
 
+// Adds v into the row at offset o of the window (o < nwin * 64).
+template <class S, typename X>
+__device__ __forceinline__ void add_off(S& sm, int lo, uint32_t o, X v, X* y) {
+    const int s = sm.slot[o >> kPgBits];
+    if (s >= 0) add_lds(&sm.acc[s * kPgRows + (int)(o & (kPgRows - 1))], v);
+    else add_global(&y[lo + (int)o], v);
+}
+
 // One global atomic per row whose partial sum is not zero (a row that got
 // no product keeps +0.0, and adding +0.0 would change nothing).  Starts
 // with a barrier.
@@ -193,9 +202,12 @@ __device__ __forceinline__ void load_val(const V* p, V (&v)[C]) {
 
 // ELL-Column: thread t of workgroup b takes the C adjacent columns
 // C (256 b + t) .. + C-1 and walks their slots twice: the first pass loads
-// the rows and marks their pages, the second loads rows and values again
-// and adds.  C = 4 needs n % 4 == 0 (every slot's column group aligned).
-// Padding slots (value +0.0) add nothing.
+// the rows and marks their pages, the second loads the values and adds.
+// Up to kEcHeld slots the rows stay in registers between the passes, as
+// 16-bit offsets into the window (0xffff: outside it, loaded again); wider
+// matrices, and windows of the full 65,536 rows, load them again.  C = 4
+// needs n % 4 == 0 (every slot's column group aligned).  Padding slots
+// (value +0.0) add nothing.
 template <typename V, typename X, int C, int kBytes>
 __global__ void __launch_bounds__(kBlock)
 k_spmv_ell_col_pg(int n, int width, int bw, const V* __restrict__ ev, const int* __restrict__ er,
@@ -221,6 +233,58 @@ k_spmv_ell_col_pg(int n, int width, int bw, const V* __restrict__ ev, const int*
     }
     for (int pg = threadIdx.x; pg < nwin; pg += kBlock) sm.slot[pg] = 0;
     __syncthreads();
+    if (width <= kEcHeld && nwin < kPgWindow) {
+        // rows held as 16-bit window offsets, two to a register
+        constexpr uint32_t kOut = 0xffffu;   // above every offset of a window under 1024 pages
+        uint32_t held[(kEcHeld * C + 1) / 2];
+        // a predicate, not a break, so that the loop unrolls and the held
+        // offsets keep compile-time register indices
+#pragma unroll
+        for (int k = 0; k < kEcHeld; ++k) {
+            if (k < width) {
+                int r[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) r[c] = -1;
+                if (live) load_idx<C>(&er[(size_t)j + (size_t)k * n], r);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const int pg = page_in(r[c], lo, nwin);
+                    mark_page(sm.slot, pg);
+                    const uint32_t o = pg >= 0 ? (uint32_t)(r[c] - lo) : kOut;
+                    const int h = k * C + c;
+                    if (h & 1) held[h >> 1] |= o << 16;
+                    else held[h >> 1] = o;
+                }
+            }
+        }
+        const int used = number_pages(sm, nwin);
+        clear_acc(sm, used);
+        if (live) {
+            X xs[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) xs[c] = x[j + c];
+#pragma unroll
+            for (int k = 0; k < kEcHeld; ++k) {
+                if (k < width) {
+                    const size_t off = (size_t)j + (size_t)k * n;
+                    V v[C];
+                    load_val<V, C>(&ev[off], v);
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        const int h = k * C + c;
+                        const uint32_t o = (held[h >> 1] >> (16 * (h & 1))) & 0xffffu;
+                        const X w = (X)widen(v[c]);
+                        if (w != (X)0) {
+                            if (o != kOut) add_off(sm, lo, o, w * xs[c], y);
+                            else add_row(sm, lo, nwin, er[off + c], w * xs[c], y);
+                        }
+                    }
+                }
+            }
+        }
+        flush(sm, used, lo, y);
+        return;
+    }
     size_t off = (size_t)j;
     for (int k = 0; k < width; ++k, off += (size_t)n) {
         int r[C];
