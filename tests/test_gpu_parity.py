@@ -676,6 +676,31 @@ def test_ccs_every_algorithm(case, alg):
     plan.close()
 
 
+def test_banded_ccs_reports_an_entry_outside_the_measured_band():
+    """The banded CRS -> CCS relies on the bandwidth measured when the plan
+    was made: after one column index moves far outside that band it reports
+    SPMV_E_MATRIX instead of a wrong CCS, and once the index is back the
+    same plan converts bit-exactly."""
+    spmvat = lib_ready()
+    m = gen.banded(20000, 3, 43)
+    irp, icol, val = to_dev(m)
+    plan = spmvat.Plan(irp, icol, val)
+    assert plan.stats.bandwidth == 3
+    p = int(m.irp[100]) + 1
+    kept = int(icol[p].item())
+    icol[p] = 15000
+    with pytest.raises(spmvat.SpmvError) as ei:
+        plan.to_ccs(algorithm=spmvat.CCS_BANDED)
+    assert ei.value.status == spmvat.SPMV_E_MATRIX
+    icol[p] = kept
+    ccp, irow_t, val_t = plan.to_ccs(algorithm=spmvat.CCS_BANDED)
+    o_ccp, o_irow_t, o_val_t = oracle.csr_to_ccs(m.n, m.irp, m.icol, m.val)
+    assert np.array_equal(host(ccp), o_ccp)
+    assert np.array_equal(host(irow_t), o_irow_t)
+    assert np.array_equal(bits(host(val_t)), bits(o_val_t))
+    plan.close()
+
+
 def one_per_row(n, seed):
     """One entry per row at a random column: nnz = n exactly."""
     rng = np.random.default_rng(seed)
