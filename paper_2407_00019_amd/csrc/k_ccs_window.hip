@@ -10,20 +10,23 @@
 //
 //   count       per wave stretch (one wave per workgroup): entries per
 //               window block.
-//   blocks      one wave per block: a scan over the tiles whose window
-//               covers the block, in tile order and wave order inside a
-//               tile, turns the counts into each stretch's start inside the
-//               block and sums the block's length; the block starts follow
-//               by the shared scan kernels.
+//   blocks      lane j of a workgroup on block 64 g + j: a scan over the
+//               tiles whose window covers the block, in tile order and wave
+//               order inside a tile, turns the counts into each stretch's
+//               start inside the block and sums the block's length.
+//   scan        the block starts, by one workgroup (by the shared scan
+//               kernels past 131,072 blocks).
 //   distribute  per tile: each wave moves its stretch, in storage order, to
-//               the blocks (equal blocks inside a group of 64 ranked by
-//               ballots), as a packed key (row, column within the block) and
-//               the value.  A block then holds its entries in CRS order.
-//               One tile's run inside a block is long, so stores coalesce.
-//   place       one workgroup per block: column counts, the column pointer,
-//               and the stable placement of the block's entries by column
-//               (per-wave counts, ballot ranks) into LDS, written out in
-//               order; blocks larger than the LDS stage write in place.
+//               the blocks (equal blocks inside a group of 64 ranked through
+//               the wave's LDS lane masks), as a packed key (row, column
+//               within the block) and the value.  A block then holds its
+//               entries in CRS order.  One tile's run inside a block is
+//               long, so stores coalesce.
+//   place       4 blocks per workgroup: column counts, the column pointer,
+//               and the stable placement of each block's entries by column
+//               (per-wave counts, ranks from LDS lane masks) into LDS,
+//               written out in order; blocks larger than the LDS stage write
+//               in place.
 //
 // CRS order inside each block, kept by a stable sort on the column, is the
 // paper's order: rows ascending, each row's entries in storage order.
@@ -31,6 +34,7 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "lane_match.h"
 
 namespace spmvat {
 
@@ -304,7 +308,10 @@ __global__ void __launch_bounds__(kBcThreads)
 k_bcs_distribute(int n, int bw, int nwbmax, int wb_bits, const int* __restrict__ irp, const int* __restrict__ icol,
                  const V* __restrict__ val, const int* __restrict__ table, const int* __restrict__ bstart,
                  uint32_t* __restrict__ key, V* __restrict__ sval) {
-    extern __shared__ int lds_d[];   // kBcWaves x nwbmax cursors, then kBcRows + 1 row pointers
+    // LDS: kBcWaves x kLaneMaskSlots lane masks, kBcWaves x nwbmax cursors,
+    // kBcRows + 1 row pointers
+    extern __shared__ unsigned long long lds_m[];
+    int* lds_d = reinterpret_cast<int*>(lds_m + kBcWaves * kLaneMaskSlots);
     int* sp = lds_d + kBcWaves * nwbmax;
     const int t = (int)xcd_block(blockIdx.x, gridDim.x);
     const int r0 = t * kBcRows, rows = min(n, r0 + kBcRows) - r0;
@@ -317,11 +324,13 @@ k_bcs_distribute(int n, int bw, int nwbmax, int wb_bits, const int* __restrict__
         lds_d[ww * nwbmax + wb] = bstart[b0 + wb] + trow[ww * nwbmax + wb];
     }
     for (int i = threadIdx.x; i <= rows; i += kBcThreads) sp[i] = irp[r0 + i];
+    for (int i = threadIdx.x; i < kBcWaves * kLaneMaskSlots; i += kBcThreads) lds_m[i] = 0;
     __syncthreads();
     int ws, we;
     stretch(sp[0], sp[rows], kBcWaves, w, ws, we);
     if (ws >= we) return;
     int* cur = lds_d + w * nwbmax;
+    unsigned long long* masks = lds_m + w * kLaneMaskSlots;
     int r = last_le(sp, 0, rows - 1, min(ws + lane, we - 1));
     const uint64_t below = lanes_below();
     for (int base = ws; base < we; base += kWave * kBcUnroll) {
@@ -341,8 +350,12 @@ k_bcs_distribute(int n, int bw, int nwbmax, int wb_bits, const int* __restrict__
             // entries outside the window (flagged by the count) are left out
             const bool valid = p < we && (unsigned)wb < (unsigned)nwb;
             if (p < we) while (sp[r + 1] <= p) ++r;
-            const uint64_t act = __ballot(valid);
-            const uint64_t m = match_low_bits((uint32_t)(valid ? wb : 0), wb_bits, act);
+            const uint32_t kw = valid ? (uint32_t)wb : 0u;
+            // equal window blocks: the low bits through the LDS lane masks,
+            // the rest (two or three bits at most) by ballots
+            uint64_t m = match_lds(kw & (kLaneMaskSlots - 1), valid, masks);
+            if (wb_bits > kLaneMaskBits)
+                m &= match_low_bits(kw >> kLaneMaskBits, wb_bits - kLaneMaskBits, __ballot(valid));
             const int rank = (int)__popcll(m & below);
             int slot = 0;
             if (valid) slot = cur[wb];
@@ -362,6 +375,7 @@ struct PlaceSmem {
     static constexpr int kCap = kPlStageBytes / (4 + (int)sizeof(V));
     int cnt[kPlWaves * kBcCols];
     int colptr[kBcCols + 1];
+    unsigned long long masks[kPlWaves][kBcCols];   // per wave: lane masks of the 64 columns
     int s_row[kCap];
     V s_val[kCap];
 };
@@ -403,13 +417,13 @@ __device__ __forceinline__ void place_columns(PlaceSmem<V>& sm, int n, int nb, i
 
 // Stable placement of one group of 64 consecutive entries of a wave's
 // stretch (p < we valid): rank among the group's entries of the same column
-// by ballots, slot from the wave's cursor of that column.
+// from the wave's LDS lane masks, slot from the wave's cursor of that column.
 template <typename V>
 __device__ __forceinline__ void place_group(PlaceSmem<V>& sm, int* mine, int p, int we, uint32_t k, V v, bool staged,
                                             int s, int* irow_t, V* val_t) {
     const bool valid = p < we;
     const uint32_t lc = k & (kBcCols - 1);
-    const uint64_t mm = match_low_bits(lc, kBcBits, __ballot(valid));
+    const uint64_t mm = match_lds(lc, valid, sm.masks[threadIdx.x / kWave]);
     const int rank = (int)__popcll(mm & lanes_below());
     int slot = 0;
     if (valid) slot = mine[lc];
@@ -468,6 +482,8 @@ k_bcs_place(int n, int nb, const int* __restrict__ bstart, const uint32_t* __res
     const int b0 = (int)xcd_block(blockIdx.x, gridDim.x) * kPlBlocks;
     const int nblk = min(kPlBlocks, nb - b0);
     const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    for (int i = threadIdx.x; i < kPlWaves * kBcCols; i += kPlThreads) (&sm.masks[0][0])[i] = 0;
+    __syncthreads();
     bool held = true;
     for (int i = 0; i < nblk; ++i) {
         const int m = bstart[b0 + i + 1] - bstart[b0 + i];
@@ -545,7 +561,7 @@ template <typename V>
 static hipError_t wccs_back_t(const WccsGeom& g, int n, int bw, const int* irp, const int* icol, const void* val,
                               const int* table, const int* bstart, uint32_t* key, void* sval, int* ccp, int* irow_t,
                               void* val_t, WccsInfo* info, hipStream_t s) {
-    const size_t lds = (size_t)kBcWaves * g.nwbmax * 4 + (size_t)(kBcRows + 1) * 4;
+    const size_t lds = (size_t)kBcWaves * kLaneMaskSlots * 8 + (size_t)kBcWaves * g.nwbmax * 4 + (size_t)(kBcRows + 1) * 4;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bcs_distribute<V>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
