@@ -741,6 +741,25 @@ def test_ccs_radix_passes(case):
     plan.close()
 
 
+@pytest.mark.parametrize("case", sorted(RADIX_CASES))
+def test_ccs_banded_small_and_ragged(case):
+    """The banded CRS -> CCS on the small cases of the radix test: tiles
+    holding fewer entries than waves (empty stretches, stretches shorter
+    than one 16-byte quad), one row, one entry per row; no entries takes
+    the plain route.  CCS bit-exact with the oracle."""
+    spmvat = lib_ready()
+    m = RADIX_CASES[case]()
+    irp, icol, val = to_dev(m)
+    plan = spmvat.Plan(irp, icol, val)
+    ccp, irow_t, val_t = plan.to_ccs(algorithm=spmvat.CCS_BANDED)
+    o_ccp, o_irow_t, o_val_t = oracle.csr_to_ccs(m.n, m.irp, m.icol, m.val)
+    assert np.array_equal(host(ccp), o_ccp)
+    assert np.array_equal(host(irow_t), o_irow_t)
+    assert np.array_equal(bits(host(val_t)), bits(o_val_t))
+    assert plan.stats.max_col == (int(np.diff(o_ccp).max()) if m.n else 0)
+    plan.close()
+
+
 @pytest.mark.parametrize("case", ["stencil27_e12", "dup_long", "rand_unsorted"])
 def test_ccs_in_place_copy_back(case):
     """The in-place CCS (Phase I with its copy-back): the plan's own CRS
