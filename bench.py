@@ -410,7 +410,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="stencil27_128", choices=["stencil27_128", "laplace64", "powerlaw"])
+    ap.add_argument("--workload", default="stencil27_128",
+                    choices=["stencil27_128", "laplace64", "powerlaw", "dsweep_d1", "dsweep_local_d1"],
+                    help="dsweep_*: the D_mat sweep's matrix at D_mat = 1 (n = 1,048,576, mean 32 per row), "
+                         "columns uniform over the row or within 4096 of the diagonal")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-precision", action="store_true", help="skip the reduced-precision rows")
     ap.add_argument("--no-extra", action="store_true",
@@ -447,7 +450,8 @@ def main():
         torch.cuda.synchronize()
         del a, b
     builders = {"laplace64": (gen.laplace_64x64, 1), "stencil27_128": (gen.stencil27_128, 2),
-                "powerlaw": (gen.powerlaw, 3)}
+                "powerlaw": (gen.powerlaw, 3), "dsweep_d1": (lambda: gen.dsweep_matrix(8), 5),
+                "dsweep_local_d1": (lambda: gen.dsweep_matrix(8, local=True), 5)}
     table, table_path = load_at_table(spmvat)
     t0 = time.time()
     build_m, cfg_index = builders[args.workload]
@@ -477,7 +481,10 @@ def main():
     if os.path.exists(tpath):
         with open(tpath) as f:
             tj = json.load(f)
-        ent = tj.get("kernels", {}).get(kernel_names[best])
+        # each workload's counters were taken on its own matrix
+        section = {"stencil27_128": "kernels", "powerlaw": "powerlaw_kernels", "dsweep_d1": "dsweep_kernels",
+                   "dsweep_local_d1": "dsweep_local_kernels"}.get(args.workload)
+        ent = tj.get(section, {}).get(kernel_names[best]) if section else None
         if ent and ent.get("source_sha") == kernel_source_sha():
             traffic = ent.get("bytes_per_launch")
     # achieved = algorithmic bytes / mean launch time of the dominant kernel
