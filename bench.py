@@ -344,7 +344,9 @@ def measure(spmvat, m, cfg_index, steps, warmup, spmv_reps, precision, table, lo
         g = gbs(b, med[key])
         per_format[name] = {"us": round(ms[key] * 1e3, 2), "median_us": round(med[key] * 1e3, 2), "gbs": round(g, 1),
                             "frac": round(g / HBM_PEAK_GBS, 4), "bytes": int(b)}
-    best = max(per_format, key=lambda k: per_format[k]["gbs"])
+    # the fastest format (a format that moves more bytes per entry would win
+    # on GB/s without being faster)
+    best = min(per_format, key=lambda k: per_format[k]["median_us"])
     t_crs0 = med["spmv_crs0"]
     t_crs1 = min(med["spmv_crs8"], med[f"spmv_crs{v_sub}"])      # the strong CRS kernel
     transforms = {}
