@@ -24,6 +24,7 @@ crosses c.
     python -m paper_2407_00019_amd.offline [--points 0,4,8] [--out FILE]
     python -m paper_2407_00019_amd.offline --refit FILE   (models only, no GPU)
     python -m paper_2407_00019_amd.offline --table1 [--out FILE]
+    python -m paper_2407_00019_amd.offline --precision-summary SWEEP.json ... --out FILE
 
 --table1 runs the same measurements on stand-ins for the paper's own 22
 test matrices (Table 1: the printed N, mean row length and D_mat; see
@@ -284,6 +285,39 @@ def calibrate_margin(cm, jobs=96, reps=5, quantile=75.0):
             "median_abs_ln_err": float(np.median(errs)), "max_abs_ln_err": float(max(errs))}
 
 
+def precision_summary(paths, c=1.0):
+    """From sweeps measured with several value types (the output of this
+    module with --dtypes f64,f32,bf16,f16): per column family and value type,
+    the D_mat - R_ell graph against the library's CRS kernel, its D* by the
+    same rule as the binary64 table, the relative L2 error of y against
+    binary64 and the SpMV speed-ups over binary64 (best CRS, ELL-Row)."""
+    out = {"c": c, "families": {}}
+    for path in paths:
+        with open(path) as f:
+            sweep = json.load(f)["sweep"]
+        for p in sweep:
+            fam = out["families"].setdefault(p["family"], {})
+            for name in ("f64", "f32", "bf16", "f16"):
+                if name not in p:
+                    continue
+                q, q64 = p[name], p.get("f64", {})
+                e = fam.setdefault(name, {"d": [], "r": [], "feasible": [], "rel_l2_vs_f64": [],
+                                          "speedup_crs_vs_f64": [], "speedup_ell_vs_f64": []})
+                e["d"].append(q["d_mat"])
+                e["r"].append(q["r_ell_best"] if "t_ell" in q else 0.0)
+                e["feasible"].append(1 if q["ell_feasible"] else 0)
+                e["rel_l2_vs_f64"].append(q.get("rel_l2_vs_f64", 0.0))
+                e["speedup_crs_vs_f64"].append(q64["t_crs_best"] / q["t_crs_best"] if q64 else 1.0)
+                e["speedup_ell_vs_f64"].append(q64["t_ell"] / q["t_ell"] if q64 and "t_ell" in q else None)
+    for fam in out["families"].values():
+        for e in fam.values():
+            t = spmvat.at_table_build(e["d"], e["r"], e["feasible"], c)
+            e["d_star"] = t.d_star if math.isfinite(t.d_star) else "inf"
+            err = e["rel_l2_vs_f64"]
+            e["rel_l2_range"] = [min(err), max(err)]
+    return out
+
+
 def main(argv=None):
     import gen
     ap = argparse.ArgumentParser()
@@ -295,12 +329,20 @@ def main(argv=None):
     ap.add_argument("--families", default="scattered,local")
     ap.add_argument("--refit", default=None, help="recompute the D-R models of an existing table and exit")
     ap.add_argument("--table1", action="store_true", help="the off-line phase on the Table 1 stand-ins")
+    ap.add_argument("--precision-summary", nargs="+", default=None, metavar="SWEEP",
+                    help="summarise sweeps measured with several value types into --out and exit (no GPU)")
     ap.add_argument("--margin-jobs", type=int, default=96,
                     help="serving-stream jobs that calibrate the k-aware margin (0: keep the default)")
     a = ap.parse_args(argv)
     if a.table1:
         out = a.out if a.out != os.path.join(_HERE, "at_table.json") else os.path.join(_HERE, "table1_standins.json")
         table1_phase(out, a.c, a.reps)
+        return
+    if a.precision_summary:
+        if a.out == os.path.join(_HERE, "at_table.json"):
+            raise SystemExit("--precision-summary needs its own --out")
+        with open(a.out, "w") as f:
+            json.dump(precision_summary(a.precision_summary, a.c), f, indent=1, default=float)
         return
     if a.refit:
         with open(a.refit) as f:

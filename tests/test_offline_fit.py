@@ -70,3 +70,30 @@ def test_derive_follows_eqs_1_to_3_for_both_crs_kernels():
     assert r["r_ell_best"] == pytest.approx(1.0)
     r = derive({"t_crs_scalar": 1.0, "t_crs_best": 1.0})
     assert r["sp_best"] is None and r["r_ell_scalar"] is None
+
+
+def test_precision_summary_of_a_two_point_sweep(tmp_path):
+    """The per-value-type summary: graph, D* by the table's rule (first D
+    whose R falls below c among feasible points), errors and speed-ups."""
+    from paper_2407_00019_amd.offline import precision_summary
+
+    def pt(d, r, t_crs, t_ell, err=None, feasible=True):
+        q = {"d_mat": d, "r_ell_best": r, "ell_feasible": feasible, "t_crs_best": t_crs, "t_ell": t_ell}
+        if err is not None:
+            q["rel_l2_vs_f64"] = err
+        return q
+
+    sweep = {"sweep": [
+        {"family": "local", "f64": pt(0.0, 2.0, 1.0, 0.5), "f32": pt(0.0, 1.5, 0.5, 0.25, 1e-7)},
+        {"family": "local", "f64": pt(0.5, 0.8, 1.0, 2.0), "f32": pt(0.5, 1.2, 0.8, 1.0, 2e-7)},
+    ]}
+    path = tmp_path / "sweep.json"
+    path.write_text(json.dumps(sweep))
+    s = precision_summary([str(path)])
+    f64, f32 = s["families"]["local"]["f64"], s["families"]["local"]["f32"]
+    assert f64["d"] == [0.0, 0.5] and f64["r"] == [2.0, 0.8]
+    assert f64["d_star"] == pytest.approx(0.5)          # R falls below 1 at D = 0.5
+    assert f32["d_star"] == "inf"                       # never below 1
+    assert f32["rel_l2_range"] == [1e-7, 2e-7]
+    assert f32["speedup_crs_vs_f64"] == [2.0, 1.25]
+    assert f32["speedup_ell_vs_f64"] == [2.0, 2.0]
