@@ -663,9 +663,11 @@ hipError_t launch_ccs_sort_long(int start, int len, u64* keys, u64* tmp, const v
 // ------------------------------------------------------------- ELL pack
 // Workgroup tile = 64 consecutive lines x 32 slots.  The tile's stored
 // entries are read contiguously (a line's entries are consecutive, and so
-// are consecutive lines'), transposed through LDS, and written one slot plane
-// at a time: 64 consecutive lines of slot k are 64 consecutive elements of
-// the slot-major arrays.  Padding: value bits 0 (+0.0), index = line.
+// are consecutive lines'), each finding its line in a table of line numbers
+// the lines first write into LDS, transposed through LDS, and written one
+// slot plane at a time: 64 consecutive lines of slot k are 64 consecutive
+// elements of the slot-major arrays.  Padding: value bits 0 (+0.0), index =
+// line.
 
 constexpr int kEllRows = 64;
 constexpr int kEllSlots = 32;
@@ -680,6 +682,7 @@ k_ell_pack(int n, int width, const int* __restrict__ ptr, const int* __restrict_
     __shared__ int pre[kEllRows + 1];
     __shared__ int sa[kEllRows];
     __shared__ int scnt[kEllRows];
+    __shared__ unsigned char line_of[kEllRows * kEllSlots];
     const int t = threadIdx.x;
     const int i0 = (int)xcd_block(blockIdx.x, gridDim.x) * kEllRows;
     const int rows = min(kEllRows, n - i0);
@@ -705,8 +708,14 @@ k_ell_pack(int n, int width, const int* __restrict__ ptr, const int* __restrict_
     }
     __syncthreads();
     const int total = pre[kEllRows];
+    // each line marks its entries' positions with its number, so that every
+    // entry finds its line with one LDS read
+    if (t < rows)
+        for (int k = 0; k < scnt[t]; ++k) line_of[pre[t] + k] = (unsigned char)t;
+    __syncthreads();
+#pragma unroll 8
     for (int f = t; f < total; f += kBlock) {
-        const int r = last_le(pre, 0, rows - 1, f);
+        const int r = line_of[f];
         const int k = f - pre[r];
         tv[k * kEllPitch + r] = val[sa[r] + k];
         ti[k * kEllPitch + r] = idx[sa[r] + k];
