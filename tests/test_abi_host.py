@@ -219,6 +219,24 @@ def test_off_line_table_is_stamped_with_the_kernel_sources():
     assert spmvat.at_table_from_json(d).k_margin == pytest.approx(d["k_margin"])
 
 
+def test_committed_measurements_match_the_kernel_sources():
+    """The committed auto-tuning table and counter summaries were taken
+    with the kernels in this tree: the auto-tuning
+    table carries the hash of the off-line phase's kernel sources and the
+    HBM traffic table the hash of all kernel sources (bench.py drops its
+    traffic figure when they differ)."""
+    import json
+    spmvat = _lib()
+    with open(os.path.join(ROOT, "paper_2407_00019_amd", "at_table.json")) as f:
+        assert json.load(f)["kernel_source_sha"] == spmvat.table_kernel_sha()
+    with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+        tj = json.load(f)
+    assert tj["source_sha"] == spmvat.kernel_source_sha()
+    for section in ("kernels", "powerlaw_kernels", "dsweep_kernels", "dsweep_local_kernels"):
+        assert tj[section], section
+        assert all(e["source_sha"] == tj["source_sha"] for e in tj[section].values())
+
+
 def test_cost_model_cell_follows_locality_and_d_bucket():
     """The k-aware choice reads the table cell of the matrix's locality class
     (bandwidth <= 65536 or not) and D_mat bucket (edges 1/16, 1/8, 1/4, 1/2,
