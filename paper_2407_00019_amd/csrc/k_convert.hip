@@ -46,23 +46,43 @@ __device__ __forceinline__ uint32_t narrow_bits(double v, int mb, int eb, int em
 }
 
 template <int TO>
+__device__ __forceinline__ uint32_t narrow_to(double v) {
+    if (TO == 1) return narrow_bits(v, 23, 8, -126, 127);
+    if (TO == 2) return narrow_bits(v, 7, 8, -126, 127);
+    return narrow_bits(v, 10, 5, -14, 15);
+}
+
+constexpr int kConvPer = 4;   // values per thread: two 16-byte loads, one 16- or 8-byte store
+
+// One pass, each thread converting 4 consecutive values (the arrays are
+// 16-byte aligned); the last thread takes the tail one value at a time.  A
+// grid of one-shot threads streams faster than a grid-stride loop here.
+template <int TO>
 __global__ void __launch_bounds__(kBlock) k_convert(int64_t m, const double* __restrict__ in, void* __restrict__ out) {
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
-        const double v = in[i];
-        if (TO == 1) reinterpret_cast<uint32_t*>(out)[i] = narrow_bits(v, 23, 8, -126, 127);
-        else if (TO == 2) reinterpret_cast<uint16_t*>(out)[i] = (uint16_t)narrow_bits(v, 7, 8, -126, 127);
-        else reinterpret_cast<uint16_t*>(out)[i] = (uint16_t)narrow_bits(v, 10, 5, -14, 15);
+    const int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * kConvPer;
+    if (i0 >= m) return;
+    if (i0 + kConvPer <= m) {
+        const double2 a = *reinterpret_cast<const double2*>(in + i0);
+        const double2 b = *reinterpret_cast<const double2*>(in + i0 + 2);
+        const uint32_t o0 = narrow_to<TO>(a.x), o1 = narrow_to<TO>(a.y), o2 = narrow_to<TO>(b.x), o3 = narrow_to<TO>(b.y);
+        if (TO == 1) *reinterpret_cast<uint4*>(reinterpret_cast<uint32_t*>(out) + i0) = make_uint4(o0, o1, o2, o3);
+        else *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(out) + i0) = make_uint2(o0 | (o1 << 16), o2 | (o3 << 16));
+        return;
+    }
+    for (int64_t i = i0; i < m; ++i) {
+        const uint32_t o = narrow_to<TO>(in[i]);
+        if (TO == 1) reinterpret_cast<uint32_t*>(out)[i] = o;
+        else reinterpret_cast<uint16_t*>(out)[i] = (uint16_t)o;
     }
 }
 
 hipError_t launch_convert(int to, int64_t m, const double* in, void* out, hipStream_t s) {
-    int64_t blocks = (m + kBlock - 1) / kBlock;
-    if (blocks > 8192) blocks = 8192;
-    if (blocks < 1) blocks = 1;
-    if (to == 1) hipLaunchKernelGGL(k_convert<1>, dim3((unsigned)blocks), dim3(kBlock), 0, s, m, in, out);
-    else if (to == 2) hipLaunchKernelGGL(k_convert<2>, dim3((unsigned)blocks), dim3(kBlock), 0, s, m, in, out);
-    else hipLaunchKernelGGL(k_convert<3>, dim3((unsigned)blocks), dim3(kBlock), 0, s, m, in, out);
+    if (m <= 0) return hipSuccess;
+    const int64_t per_block = (int64_t)kBlock * kConvPer;
+    const dim3 grid((unsigned)((m + per_block - 1) / per_block));
+    if (to == 1) hipLaunchKernelGGL(k_convert<1>, grid, dim3(kBlock), 0, s, m, in, out);
+    else if (to == 2) hipLaunchKernelGGL(k_convert<2>, grid, dim3(kBlock), 0, s, m, in, out);
+    else hipLaunchKernelGGL(k_convert<3>, grid, dim3(kBlock), 0, s, m, in, out);
     return hipGetLastError();
 }
 

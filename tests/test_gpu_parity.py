@@ -406,6 +406,10 @@ def test_convert_values_bits_match_oracle():
         got = stored_bits(spmvat.convert_values(vd, dt))
         want = oracle.round_values(dt, v)
         assert np.array_equal(got, want), dt
+        # short arrays and ragged tails: four values a thread, the rest one by one
+        for m in list(range(1, 10)) + [v.shape[0] - 3]:
+            got = stored_bits(spmvat.convert_values(vd[:m].contiguous(), dt))
+            assert np.array_equal(got, want[:m]), (dt, m)
 
 
 def band_edges(n, bw, seed):
